@@ -1,0 +1,113 @@
+"""Pins of the oracle's discrete adjoint (no GPU): the per-cell Jacobian
+against central differences of the collision, an exact dot-product test of
+the transposed streaming with bounce-back, and the full reverse sweep against
+FP64 central differences of the whole rollout."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1112_0850_amd import inputs as I
+from tests import lattice_ref as R
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_collision_jacobian_vs_central_differences(seed):
+    _, w, _ = R.e_w_opp()
+    rng = np.random.default_rng(seed)
+    f = w * (1 + 0.1 * rng.standard_normal(19))
+    tau = 0.55 + 0.5 * rng.random()
+    F = 1e-2 * rng.standard_normal(3)
+    J, JF = O.collide_jacobian(tau, F, f)
+    h = 1e-6
+    Jfd = np.zeros((19, 19))
+    for j in range(19):
+        d = np.zeros(19)
+        d[j] = h
+        Jfd[:, j] = (O.collide(tau, F, f + d) - O.collide(tau, F, f - d)) / (2 * h)
+    JFfd = np.zeros((19, 3))
+    for a in range(3):
+        d = np.zeros(3)
+        d[a] = h
+        JFfd[:, a] = (O.collide(tau, F + d, f) - O.collide(tau, F - d, f)) / (2 * h)
+    assert np.abs(J - Jfd).max() < 1e-9 * np.abs(J).max()
+    assert np.abs(JF - JFfd).max() < 1e-9 * np.abs(JF).max()
+
+
+def test_transposed_streaming_dot_product_exact():
+    """<P x, y> == <x, P^T y> for pull + bounce-back (tau = inf, F = 0 makes
+    the collision Jacobian the identity); integer data make it exact."""
+    shape = (5, 4, 6)
+    flags = I.random_flags(shape, 3, solid_fraction=0.25)
+    rng = np.random.default_rng(8)
+    x = rng.integers(-50, 50, size=(19,) + shape).astype(np.float64)
+    y = rng.integers(-50, 50, size=(19,) + shape).astype(np.float64)
+    x[:, flags == 1] = 0
+    y[:, flags == 1] = 0
+    Px = O.stream(x, flags, n=1)
+    # f*(n) only enters through the collision Jacobian, which is I here;
+    # any valid state works.
+    _, w, _ = R.e_w_opp()
+    fn = np.broadcast_to(w[:, None, None, None], x.shape).copy()
+    fn[:, flags == 1] = 0
+    PTy, dF = O.adjoint_step(fn, y, np.inf, (0, 0, 0), flags)
+    assert (Px * y).sum() == (x * PTy).sum()
+    assert not PTy[:, flags == 1].any()
+
+
+def rollout_loss(u0, F, flags, tau, steps, target):
+    """L = mean over fluid cells and components of (u_T - u*)^2."""
+    shape = u0.shape[1:]
+    f = O.init(shape, flags, None, u0)
+    f = O.step(f, tau, F, flags, n=steps)
+    _, u = O.macroscopics(f, F, flags)
+    fl = np.ones(shape, bool) if flags is None else (flags & 1) == 0
+    return ((u - target) ** 2)[:, fl].mean()
+
+
+def rollout_grad(u0, F, flags, tau, steps, target):
+    shape = u0.shape[1:]
+    fl = np.ones(shape, bool) if flags is None else (flags & 1) == 0
+    states = [O.init(shape, flags, None, u0)]
+    for _ in range(steps):
+        states.append(O.step(states[-1], tau, F, flags, n=1))
+    _, uT = O.macroscopics(states[-1], F, flags)
+    gu = np.zeros_like(uT)
+    gu[:, fl] = 2 * (uT - target)[:, fl] / (3 * fl.sum())
+    lam, dF = O.adjoint_seed(states[-1], None, gu, F, flags)
+    for n in range(steps - 1, -1, -1):
+        lam, d = O.adjoint_step(states[n], lam, tau, F, flags)
+        dF += d
+    du0, _ = O.adjoint_init(lam, u0, flags)
+    return du0, dF
+
+
+@pytest.mark.parametrize("solids", [False, True])
+def test_full_adjoint_vs_central_differences(solids):
+    n, tau, steps = 8, 0.6, 25
+    shape = (n, n, n)
+    flags = None
+    if solids:
+        flags = I.random_flags(shape, 31, solid_fraction=0.15, noforce_fraction=0.2)
+    u0 = I.smooth_field(n, 2024, amplitude=0.02, modes=4)
+    target = I.smooth_field(n, 7, amplitude=0.02, modes=4)
+    F = np.array([1e-4, -5e-5, 2e-5])
+    if flags is not None:
+        u0[:, flags & 1 == 1] = 0
+    du0, dF = rollout_grad(u0, F, flags, tau, steps, target)
+    # central differences at eps and eps/2, Richardson-extrapolated so the
+    # O(eps^2) truncation cancels (the remaining error is O(eps^4)).
+    def fd(fun, eps):
+        d1 = (fun(eps) - fun(-eps)) / (2 * eps)
+        d2 = (fun(eps / 2) - fun(-eps / 2)) / eps
+        return (4 * d2 - d1) / 3
+
+    for k, s in enumerate([101, 102]):
+        v = I.smooth_field(n, s, amplitude=1.0, modes=4)
+        ref = fd(lambda e: rollout_loss(u0 + e * v, F, flags, tau, steps, target), 1e-4)
+        ad = (du0 * v).sum()
+        assert abs(ad - ref) <= 1e-8 * abs(ref), (k, ad, ref)
+    for a in range(3):
+        d = np.zeros(3)
+        d[a] = 1.0
+        ref = fd(lambda e: rollout_loss(u0, F + e * d, flags, tau, steps, target), 1e-5)
+        assert abs(dF[a] - ref) <= 1e-8 * abs(ref), (a, dF[a], ref)

@@ -1,0 +1,130 @@
+"""The oracle's pins are sensitive: each plausible mistake planted in a copy
+of the oracle source (a dropped or altered term, a wrong sign, a wrong index)
+is caught by at least one pin.  Runs on the CPU only; the planted copies are
+compiled into a temporary directory and never used elsewhere."""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from tests import test_oracle_adjoint as TA
+from tests import test_oracle_dynamics as TD
+from tests import test_oracle_lattice as TL
+from tests import test_oracle_streaming as TS
+
+SRC = os.path.join(os.path.dirname(O.__file__), "lbm_oracle.c")
+
+
+def _eq():
+    TL.test_equilibrium_moments(1.03, (0.05, -0.02, 0.01))
+
+
+def _guo():
+    TL.test_guo_moments(1 / 0.8)
+
+
+def _collide():
+    TL.test_collision_conserves_and_relaxes()
+
+
+def _stream():
+    TS.test_bounce_back_streaming_brute_force((4, 5, 6), 3)
+
+
+def _poiseuille():
+    TD.test_poiseuille_exact_steady_state(0.6)
+
+
+def _tgv():
+    TD.test_taylor_green_decay()
+
+
+def _jac():
+    TA.test_collision_jacobian_vs_central_differences(0)
+
+
+def _dot():
+    TA.test_transposed_streaming_dot_product_exact()
+
+
+def _full_adj():
+    TA.test_full_adjoint_vs_central_differences(True)
+
+
+def _conservation():
+    TD.test_conservation(False)
+
+
+# (planted change: old text -> new text, first occurrence only; pins that must fail)
+MUTATIONS = {
+    "equilibrium_second_order": ("4.5 * cu * cu - 1.5 * uu);\n  }", "4.0 * cu * cu - 1.5 * uu);\n  }",
+                                 [_eq, _tgv]),
+    "equilibrium_uu_term": ("4.5 * cu * cu - 1.5 * uu);\n  }", "4.5 * cu * cu - 0.5 * uu);\n  }",
+                            [_eq]),
+    "guo_prefactor_sign": ("S[i] = (1.0 - 0.5 * omega)", "S[i] = (1.0 + 0.5 * omega)", [_guo]),
+    "guo_dropped_u_term": ("(3.0 * (cF - uF) + 9.0 * cu * cF)", "(3.0 * cF + 9.0 * cu * cF)",
+                           [_guo, _poiseuille]),
+    "half_force_in_velocity": ("u[d] = (j[d] + 0.5 * F[d]) / rho;\n  double feq",
+                               "u[d] = j[d] / rho;\n  double feq", [_poiseuille, _collide]),
+    "relaxation_sign": ("fout[i] = f[i] - omega * (f[i] - feq[i])",
+                        "fout[i] = f[i] + omega * (f[i] - feq[i])", [_collide, _tgv]),
+    "bounce_back_not_reversed": ("dst[c * Q + OPP[i]] = src[c * Q + i];",
+                                 "dst[c * Q + i] = src[c * Q + i];", [_stream, _poiseuille]),
+    "macroscopic_force_shift": ("(m[d] - 0.5 * Fc[d]) / r", "(m[d] + 0.5 * Fc[d]) / r",
+                                [_poiseuille]),
+    "weight_of_diagonals": ("(n2 == 1) ? 1.0 / 18.0 : 1.0 / 36.0", "(n2 == 1) ? 1.0 / 18.0 : 1.0 / 37.0",
+                            [_eq, _conservation]),
+    "jacobian_velocity_derivative": ("* (C[jj][a] - u[a]) / rho;", "* (C[jj][a] + u[a]) / rho;",
+                                     [_jac]),
+    "jacobian_force_half": ("(omega * dfeq_du[a] + dS_du[a]) / (2.0 * rho);",
+                            "(omega * dfeq_du[a] + dS_du[a]) / rho;", [_jac]),
+    "adjoint_transpose_index": ("mu[t * Q + i] : mu[c * Q + OPP[i]]", "mu[t * Q + i] : mu[c * Q + i]",
+                                [_dot]),
+    "adjoint_seed_force_sign": ("acc[d] += -gu[d] / (2.0 * rho[c]);", "acc[d] += gu[d] / (2.0 * rho[c]);",
+                                [_full_adj]),
+    "adjoint_init_dropped_term": ("9.0 * cu * C[i][a] - 3.0 * u[a]);\n      }\n    }\n    for (int a = 0; a < 3; ++a) dL_du0",
+                                  "9.0 * cu * C[i][a]);\n      }\n    }\n    for (int a = 0; a < 3; ++a) dL_du0",
+                                  [_full_adj]),
+}
+
+
+@pytest.fixture(scope="module")
+def workdir():
+    with tempfile.TemporaryDirectory() as d:
+        yield d
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_planted_mistake_is_caught(name, workdir):
+    old, new, checks = MUTATIONS[name]
+    src = open(SRC).read()
+    assert old in src, f"mutation anchor for {name} not found"
+    mutated = src.replace(old, new, 1)
+    cpath = os.path.join(workdir, f"{name}.c")
+    lpath = os.path.join(workdir, f"lib{name}.so")
+    open(cpath, "w").write(mutated)
+    subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+                    "-o", lpath, cpath, "-lm"], check=True)
+    saved = O._lib
+    O._lib = O.load(lpath)
+    try:
+        caught = []
+        for chk in checks:
+            try:
+                chk()
+                caught.append(False)
+            except AssertionError:
+                caught.append(True)
+        assert any(caught), f"no pin caught the planted mistake {name}"
+        # every listed pin is expected to catch it
+        assert all(caught), f"{name}: caught by {[c.__name__ for c, k in zip(checks, caught) if k]}"
+    finally:
+        O._lib = saved
+
+
+def test_unmutated_oracle_passes_the_same_checks():
+    for chk in {c for _, _, cs in MUTATIONS.values() for c in cs}:
+        chk()
