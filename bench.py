@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""Benchmark of the D3Q19 BGK hot path on one MI355X.
+
+Workload (the headline): porous periodic box 512^3, 10% solid from random
+non-overlapping spheres of radius 4-12 (seed 12345), tau = 0.55, body force
+g_x = 1e-6, fluid initially at rest; FP32 offset storage.  One "step" is one
+fused stream-collide update of the whole box (one kernel launch).  Reported
+beside it, on the same geometry: FP16-offset and BF16-offset storage (FP32
+collide) and FP64 storage; the adjoint/forward time ratio of the
+differentiable rollout (periodic 128^3, 400 steps, checkpoints every 20);
+the STREAM-copy bandwidth of the GPU; and the FP64 CPU oracle timed on this
+host's cores on a bounded sample (the 128^3 crop of the same geometry).
+
+Output: one JSON line on stdout.  Inputs are synthetic and seeded, resident
+in HBM before the timed region starts.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_1112_0850_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_porous512_f32.json")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=512, help="edge of the cubic porous box")
+    ap.add_argument("--only", default="", help="comma list of legs: f32,f16,bf16,f64,adjoint,copy,cpu")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def timed_steps(sim, torch, steps, warmup):
+    """Average ms per fused step over `steps` launches, HIP events on the
+    solver's stream, bracketed by device synchronisation."""
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s=0):
+    from paper_1112_0850_amd import _abi as A
+    n = round(n_cells ** (1 / 3))
+    sim = LBM((n, n, n), 0.55, (1e-6, 0.0, 0.0), storage, flags=flags_t, f16_scale_log2=s)
+    ms = timed_steps(sim, torch, steps, warmup)
+    r = sim.reduce().cpu().numpy()
+    bpu = A.lbm_bytes_per_update(sim.storage)
+    alg_bytes = bpu * n_fluid + n_cells  # populations of fluid cells + one flag byte per cell
+    out = {
+        "storage": storage, "ms_per_step": ms,
+        "mlups": n_cells / ms / 1e3, "mflups": n_fluid / ms / 1e3,
+        "bytes_per_update": bpu, "alg_bytes_per_step": alg_bytes,
+        "alg_gbs": alg_bytes / ms / 1e6, "hbm_frac": alg_bytes / ms / 1e6 / HBM_PEAK_GBS,
+        "mass": float(r[0]), "finite": bool(all(map(lambda v: v == v, r))),
+    }
+    if storage == "f16":
+        out["f16_scale_log2"] = s
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def copy_leg(torch):
+    from paper_1112_0850_amd.lbm import stream_copy
+    nbytes = 4 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    c = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(3):
+        stream_copy(c, a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        stream_copy(c, a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, c
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * nbytes, "ms": ms, "gbs": 2 * nbytes / ms / 1e6}
+
+
+def adjoint_leg(torch, n=128, steps=400, k=20):
+    """Forward vs backward time of the differentiable rollout (128^3 periodic,
+    smooth random u0 amplitude 0.02, g = (1e-6, 0, 0), tau = 0.6)."""
+    from paper_1112_0850_amd import inputs as I
+    from paper_1112_0850_amd import _abi as A
+    from paper_1112_0850_amd.lbm import LBM, rollout
+    u0 = torch.from_numpy(I.smooth_field(n, 2024, amplitude=0.02)).float().cuda()
+    target = torch.from_numpy(I.smooth_field(n, 7, amplitude=0.02)).float().cuda()
+    g = torch.tensor([1e-6, 0.0, 0.0], dtype=torch.float64, requires_grad=True)
+    u0.requires_grad_(True)
+
+    def run():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rho, u = rollout(u0, g, steps=steps, tau=0.6, checkpoint_every=k)
+        loss = ((u - target) ** 2).mean()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+
+    run()  # warm-up (allocations, first launches)
+    u0.grad = None
+    g.grad = None
+    tf, tb = run()
+    # pure kernel times at the same size: forward step vs adjoint step
+    sim = LBM((n, n, n), 0.6, (1e-6, 0, 0), "f32", u0=u0.detach())
+    ms_fwd = timed_steps(sim, torch, 200, 20)
+    lam = [torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda") for _ in range(2)]
+    part = torch.zeros(sim.adj_partials_bytes // 8, dtype=torch.float64, device="cuda")
+    import ctypes
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    fst = sim.grids[sim.current]
+    for _ in range(10):
+        A.lbm_adjoint_step(sim.ctx, P(fst), P(lam[0]), P(lam[1]), P(part))
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    for i in range(200):
+        A.lbm_adjoint_step(sim.ctx, P(fst), P(lam[i & 1]), P(lam[(i + 1) & 1]), P(part))
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    ms_adj = e0.elapsed_time(e1) / 200
+    cells = n ** 3
+    out = {
+        "workload": f"periodic {n}^3 FP32, tau 0.6, {steps} steps, checkpoints every {k}",
+        "forward_s": tf, "backward_s": tb, "bwd_over_fwd": tb / tf,
+        "fwd_step_ms": ms_fwd, "adj_step_ms": ms_adj, "adj_kernel_over_fwd_kernel": ms_adj / ms_fwd,
+        "adj_kernel_alg_gbs": 228 * cells / ms_adj / 1e6,
+        "grad_finite": bool(torch.isfinite(u0.grad).all().item() and torch.isfinite(g.grad).all().item()),
+    }
+    del sim, lam, part
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_leg(flags_np, seconds):
+    """The FP64 oracle (plain loops, OpenMP) on the 128^3 crop of the same
+    geometry, timed on this host: a bounded sample of about `seconds`."""
+    import numpy as np
+    from oracle import oracle as O
+    crop = np.ascontiguousarray(flags_np[:128, :128, :128])
+    shape = crop.shape
+    f = O.init(shape, crop)
+    t0 = time.perf_counter()
+    f = O.step(f, 0.55, (1e-6, 0, 0), crop, n=1)
+    t1 = time.perf_counter() - t0
+    nsteps = max(1, int(seconds / max(t1, 1e-3)))
+    t0 = time.perf_counter()
+    O.step(f, 0.55, (1e-6, 0, 0), crop, n=nsteps)
+    dt = time.perf_counter() - t0
+    cells = int(np.prod(shape))
+    fluid = int((crop & 1 == 0).sum())
+    return {"value": cells * nsteps / dt / 1e6, "unit": "MLUPS", "cores": O.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle, {nsteps} steps of the 128^3 crop of the porous geometry "
+                      f"({fluid} fluid cells), {dt:.1f} s",
+            "mflups": fluid * nsteps / dt / 1e6, "host_copy_gbs": O.host_copy_gbs()}
+
+
+def traffic_entry(alg_bytes, ms):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    or None when the kernel source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE))
+    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if t.get("kernels_sha256") != src_hash:
+        return None
+    return t.get("traffic_bytes_per_launch")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "domain decomposition is a design note, not part of this build", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+    from paper_1112_0850_amd import inputs as I
+    from paper_1112_0850_amd.lbm import LBM
+
+    legs = set(args.only.split(",")) if args.only else {"f32", "f16", "bf16", "f64", "adjoint",
+                                                        "copy", "cpu"}
+    n = args.n
+    log(f"geometry: {n}^3 sphere pack, 10% solid, seed 12345")
+    flags = I.sphere_pack((n, n, n), 0.10, seed=12345)
+    n_cells = n ** 3
+    n_fluid = int((flags & 1 == 0).sum())
+    flags_t = torch.from_numpy(flags).cuda()
+    res = {}
+    if "copy" in legs:
+        log("copy probe")
+        res["copy"] = copy_leg(torch)
+    for st, s in (("f32", 0), ("f16", 12), ("bf16", 0), ("f64", 0)):
+        if st in legs:
+            log(f"forward {st}")
+            res[st] = forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st, args.steps,
+                                  args.warmup, s)
+            log(f"  {res[st]['mlups']:.0f} MLUPS, {res[st]['alg_gbs']:.0f} GB/s algorithmic")
+    if "adjoint" in legs:
+        log("adjoint 128^3")
+        res["adjoint"] = adjoint_leg(torch)
+    if "cpu" in legs:
+        log("cpu oracle sample")
+        res["cpu"] = cpu_leg(flags, args.cpu_seconds)
+
+    main_leg = res.get("f32") or next((res[k] for k in ("f16", "bf16", "f64") if k in res), None)
+    line = {
+        "metric": "MLUPS & %HBM roofline, D3Q19 512^3 FP32 vs FP16-offset; adjoint/fwd time",
+        "value": main_leg["mlups"] if main_leg else None,
+        "unit": "MLUPS",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": main_leg["ms_per_step"] if main_leg else None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16": "f16", "bf16": "bf16", "f64": "f64"}[main_leg["storage"]]
+        if main_leg else None,
+        "data": "synthetic",
+        "config": {"workload": f"D3Q19 BGK porous periodic box {n}^3, 10% solid random spheres "
+                               f"r 4-12 (seed 12345), tau 0.55, g_x 1e-6, from rest, "
+                               f"{main_leg['storage'] if main_leg else ''} offset storage",
+                   "cells": n_cells, "fluid_cells": n_fluid},
+    }
+    if main_leg:
+        line["roofline"] = {
+            "bound": "hbm", "achieved": main_leg["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": main_leg["hbm_frac"],
+            "traffic": traffic_entry(main_leg["alg_bytes_per_step"], main_leg["ms_per_step"]),
+            "kernel": "k_step<F32, solids, force>",
+            "alg_bytes_per_launch": main_leg["alg_bytes_per_step"],
+        }
+    if "cpu" in res:
+        line["cpu_baseline"] = res["cpu"]
+    line["mflups"] = main_leg["mflups"] if main_leg else None
+    for st in ("f16", "bf16", "f64"):
+        if st in res:
+            line[f"{st}_storage"] = res[st]
+    if "f16" in res and "f32" in res:
+        line["f16_over_f32"] = res["f16"]["mlups"] / res["f32"]["mlups"]
+    if "adjoint" in res:
+        line["adjoint"] = res["adjoint"]
+    if "copy" in res:
+        line["copy_gbs"] = res["copy"]["gbs"]
+        if main_leg:
+            line["frac_of_copy_bw"] = main_leg["alg_gbs"] / res["copy"]["gbs"]
+    line["context"] = "paper: 650 MLUPS SP / 290 MLUPS DP on an NVIDIA Tesla C2070 (other hardware)"
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

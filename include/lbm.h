@@ -1,0 +1,216 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D3Q19 BGK lattice Boltzmann hot path.
+ *
+ * Method: Habich et al., "Performance engineering for the Lattice Boltzmann
+ * method on GPGPUs" (Sec. 2, Eq. (1)): the BGK evolution equation on the
+ * D3Q19 lattice with the equilibrium of Qian et al. (1992), updated with the
+ * fused stream-collide ("pull") ordering and two lattices of Sec. 6; obstacle
+ * cells handled by bounce-back (Sec. 2, last paragraph) in its half-way form;
+ * body force by Guo, Zheng & Shi (Phys. Rev. E 65, 046308, 2002).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Lattice units (dx = dt = 1), c_s^2 = 1/3, nu = (tau - 1/2)/3.
+ *  - Direction order i = 0..18 of every population array:
+ *       0:( 0, 0, 0)  1:(+1, 0, 0)  2:(-1, 0, 0)  3:( 0,+1, 0)  4:( 0,-1, 0)
+ *       5:( 0, 0,+1)  6:( 0, 0,-1)  7:(+1,+1, 0)  8:(-1,-1, 0)  9:(+1,-1, 0)
+ *      10:(-1,+1, 0) 11:(+1, 0,+1) 12:(-1, 0,-1) 13:(+1, 0,-1) 14:(-1, 0,+1)
+ *      15:( 0,+1,+1) 16:( 0,-1,-1) 17:( 0,+1,-1) 18:( 0,-1,+1)
+ *    weights 1/3 (i = 0), 1/18 (i = 1..6), 1/36 (i = 7..18); opposite pairs
+ *    (1,2) (3,4) (5,6) (7,8) (9,10) (11,12) (13,14) (15,16) (17,18).
+ *  - Population grid ("grid"): structure of arrays [19][nz][ny][x_stride],
+ *    x contiguous, x_stride >= nx from lbm_query (padding cells after each
+ *    x-row, never computed -- the paper's Sec. 6 alignment padding).  Each
+ *    element holds the OFFSET g_i = f_i - w_i of the post-collision
+ *    population f*_i after the latest step, in the storage type:
+ *      LBM_F32  float,  LBM_F64 double,  LBM_BF16 bfloat16 (g),
+ *      LBM_F16  IEEE binary16 holding 2^s * g, s = f16_scale_log2.
+ *    Every store rounds to nearest-even.  Collision arithmetic is FP32 for
+ *    F32/F16/BF16 storage and FP64 for F64 storage.
+ *  - Scalar fields are [nz][ny][nx], vector fields [3][nz][ny][nx] (no
+ *    padding).  flags are uint8 [nz][ny][nx]: bit0 LBM_FLAG_SOLID (obstacle
+ *    cell, never read or written), bit1 LBM_FLAG_NOFORCE (fluid cell without
+ *    body force); other bits must be 0.  flags == NULL means all fluid.
+ *  - All axes are periodic; walls are rows of solid cells.
+ *  - Time levels: after lbm_init the current grid holds f*(0) = f^eq(rho0,u0)
+ *    (solid cells 0); each step streams with half-way bounce-back and then
+ *    collides:  f*_i(x, t+1) = Omega_i( f_i(x, t+1) ),
+ *      f_i(x, t+1) = f*_i(x - c_i, t)  if x - c_i is fluid, else f*_{opp i}(x, t).
+ *  - Every pointer is device memory owned by the caller, 256-byte aligned,
+ *    and must stay valid while work that uses it is queued.  Calls enqueue
+ *    on the context's stream and return without synchronising; nothing in
+ *    this library allocates device memory.
+ *  - Errors: every call returns lbm_status; LBM_OK = 0.  Invalid arguments
+ *    are detected on the host before anything is enqueued (LBM_E_ARG) and
+ *    leave the context unchanged.  lbm_last_error() gives a message for the
+ *    calling thread's latest failure.  No C++ exception crosses this ABI.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Only the declarations below are exported from the shared library. */
+#pragma GCC visibility push(default)
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_ARG = -1,         /* invalid argument (host-side validation) */
+  LBM_E_HIP = -2,         /* a HIP runtime call or kernel launch failed */
+  LBM_E_UNSUPPORTED = -3, /* valid but not supported (e.g. too large) */
+  LBM_E_STATE = -4        /* call not valid for this context's state */
+} lbm_status;
+
+typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2, LBM_F64 = 3 } lbm_storage;
+
+enum { LBM_FLAG_SOLID = 1, LBM_FLAG_NOFORCE = 2 };
+
+typedef struct {
+  int32_t nx, ny, nz;     /* cells per axis, each >= 1 */
+  int32_t storage;        /* lbm_storage */
+  int32_t f16_scale_log2; /* s in [-24, 24]; used by LBM_F16 only */
+  int32_t x_align;        /* x_stride is rounded up to a multiple of this many
+                             cells; 0 = default (64), 1 = no padding */
+  double tau;             /* BGK relaxation time, > 1/2, or +INFINITY
+                             (omega = 0: pure streaming, a test mode) */
+  double force[3];        /* Guo body-force density, finite */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Sizes the caller must allocate for `p` (any output pointer may be NULL):
+ *   x_stride       padded x extent of a grid row, in cells;
+ *   grid_bytes     bytes of ONE population grid (two are needed);
+ *   scratch_bytes  bytes of the reduction scratch passed to lbm_init;
+ *   adj_partials_bytes  bytes of the dL/dF partial-sum buffer of the adjoint.
+ * Errors: LBM_E_ARG for invalid parameters, LBM_E_UNSUPPORTED when one
+ * direction's array would exceed 4 GiB - 1 or a grid exceeds 2^31 cells. */
+lbm_status lbm_query(const lbm_params* p, int64_t* x_stride, size_t* grid_bytes,
+                     size_t* scratch_bytes, size_t* adj_partials_bytes);
+
+/* Algorithmic HBM bytes of one fluid-cell update for a storage type: 19 loads
+ * + 19 stores of one population (Sec. 4 byte model: 152 for FP32, 304 for
+ * FP64; 76 for the 16-bit offset storage).  Returns 0 for an unknown type. */
+int32_t lbm_bytes_per_update(int32_t storage);
+
+/* Copies the D3Q19 tables in the interface order above: e[19][3], w[19],
+ * opp[19] (any pointer may be NULL).  Host memory; needs no GPU. */
+void lbm_lattice(int32_t* e, double* w, int32_t* opp);
+
+/* Creates a context over caller-owned memory and enqueues the initial state
+ * f*(0) = f^eq(rho0, u0) (Sec. 2 step 2 equilibrium) on fluid cells of
+ * grid_a; solid cells and padding of both grids are set to 0.
+ *   grid_a, grid_b  two grids of grid_bytes (the two lattices of Sec. 2);
+ *   flags           uint8 [nz][ny][nx] or NULL (all fluid);
+ *   scratch         scratch_bytes of device memory for lbm_reduce;
+ *   rho0            float [nz][ny][nx] or NULL (uniform 1);
+ *   u0              float [3][nz][ny][nx] or NULL (rest);
+ *   stream          a hipStream_t (NULL = default stream).
+ * flags, scratch and the grids must outlive the context.  *out receives the
+ * context (host memory, freed by lbm_destroy).
+ * Errors: LBM_E_ARG (NULL out/p/grids/scratch, misaligned pointers, bad
+ * params), LBM_E_UNSUPPORTED (size limits), LBM_E_HIP (launch failure). */
+lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* grid_a, void* grid_b,
+                    const uint8_t* flags, void* scratch, const float* rho0,
+                    const float* u0, void* stream);
+
+/* Enqueues n >= 0 fused stream-collide steps (pull streaming with half-way
+ * bounce-back, moments, equilibrium, BGK relaxation with Guo forcing: Sec. 2
+ * steps 1-3, Eq. (1)), alternating between the two grids.
+ * Errors: LBM_E_ARG (NULL ctx, n < 0), LBM_E_HIP (launch failure). */
+lbm_status lbm_step(lbm_ctx* ctx, int32_t n);
+
+/* One step from an arbitrary grid `src` (state f*(t), same layout) into
+ * `dst` (receives f*(t+1)); the context's own grids and time are untouched.
+ * src and dst must differ.  Used to recompute forward states for the adjoint.
+ * Errors: LBM_E_ARG, LBM_E_HIP. */
+lbm_status lbm_step_from(lbm_ctx* ctx, const void* src, void* dst);
+
+/* Macroscopic fields of the current time level t from the stored f*(t):
+ * rho = sum f*_i, rho u = sum f*_i c_i - F/2 (equal to the pre-collision
+ * moments of step t under Guo forcing; F = 0 on no-force cells).  Solid
+ * cells get rho = 0, u = 0.  Either output may be NULL.  The _f64 variant
+ * computes and writes in FP64.  Errors: LBM_E_ARG, LBM_E_HIP. */
+lbm_status lbm_macroscopics(lbm_ctx* ctx, float* rho, float* u);
+lbm_status lbm_macroscopics_f64(lbm_ctx* ctx, double* rho, double* u);
+
+/* Global FP64 sums over fluid cells of the current time level:
+ * out5 = {sum rho, sum rho u_x, sum rho u_y, sum rho u_z, sum rho |u|^2 / 2},
+ * written to DEVICE memory out5 (5 doubles).  Deterministic (fixed-order
+ * two-pass tree reduction, no atomics); uses the context's scratch.
+ * Errors: LBM_E_ARG, LBM_E_HIP. */
+lbm_status lbm_reduce(lbm_ctx* ctx, double* out5);
+
+/* Context state: which grid (0 = grid_a, 1 = grid_b) holds f*(t), the step
+ * count t, and the stream.  lbm_set_current declares that grid `parity`
+ * holds f*(t) (for restoring a saved state). */
+int32_t lbm_current(const lbm_ctx* ctx);
+int64_t lbm_time(const lbm_ctx* ctx);
+lbm_status lbm_set_current(lbm_ctx* ctx, int32_t parity, int64_t t);
+lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
+
+/* Device-to-device copy of the current grid to `dst` (lbm_save), or of `src`
+ * into the current grid with time t (lbm_restore); grid_bytes each, enqueued
+ * on the context's stream.  Checkpoint / resume.  Errors: LBM_E_ARG, LBM_E_HIP. */
+lbm_status lbm_save(lbm_ctx* ctx, void* dst);
+lbm_status lbm_restore(lbm_ctx* ctx, const void* src, int64_t t);
+
+/* ---- discrete adjoint (LBM_F32 storage only) ------------------------------
+ * Reverse mode of the update above for an objective L of the final
+ * macroscopic fields.  lambda^n = dL/d f*(n) is FP32 in the grid layout
+ * ([19][nz][ny][x_stride] floats); its solid-cell and padding slots must be
+ * zero when first used (the seed writes zeros there and the step never
+ * writes them).  dL/dF is accumulated per thread block in an FP64 partials
+ * buffer (adj_partials_bytes) without atomics; lbm_adjoint_finish_dF reduces
+ * it in a fixed order.  Errors: LBM_E_UNSUPPORTED for non-F32 storage,
+ * LBM_E_ARG, LBM_E_HIP. */
+
+/* Seed from dL/drho_T (float [nz][ny][nx] or NULL = 0) and dL/du_T (float
+ * [3][nz][ny][nx] or NULL = 0) at the current time level:
+ *   lambda^T_i = dL/drho + dL/du . (c_i - u)/rho;
+ * (re)initialises the partials with the term -dL/du / (2 rho). */
+lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const float* dL_drho, const float* dL_du,
+                            float* lam_T, double* dLdF_partials);
+
+/* One reverse step n+1 -> n:  recompute f(n+1) = stream(fstar_n), apply the
+ * transposed collision Jacobian mu = (dOmega/df)^T lambda^{n+1}, add
+ * (dOmega/dF)^T lambda^{n+1} to the partials, and push-store the transposed
+ * streaming:  lambda^n_i(x - c_i) = mu_i(x) if x - c_i is fluid, else
+ * lambda^n_{opp i}(x) = mu_i(x).  fstar_n is the forward state f*(n) in the
+ * grid layout; lam_np1 and lam_n must differ. */
+lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* fstar_n, const float* lam_np1,
+                            float* lam_n, double* dLdF_partials);
+
+/* Initial-state adjoint: dL/du0 = sum_i lambda^0_i d f^eq_i/du (rho0, u0),
+ * written as float [3][nz][ny][nx] (0 on solid cells).  rho0 / u0 as passed
+ * to lbm_init (u0 NULL = rest, rho0 NULL = 1). */
+lbm_status lbm_adjoint_init(lbm_ctx* ctx, const float* lam_0, const float* rho0,
+                            const float* u0, float* dL_du0);
+
+/* Fixed-order reduction of the partials into dLdF3 (3 doubles, device). */
+lbm_status lbm_adjoint_finish_dF(lbm_ctx* ctx, const double* dLdF_partials, double* dLdF3);
+
+/* ---- measurement ---------------------------------------------------------
+ * STREAM copy c = a (the paper's Sec. 3 case study) over n_bytes of device
+ * memory on `stream`, for the attainable-bandwidth denominator.  Both
+ * pointers 256-byte aligned, n_bytes a multiple of 16. */
+lbm_status lbm_stream_copy(void* c, const void* a, size_t n_bytes, void* stream);
+
+/* Destroys a context (host memory only; device memory stays the caller's). */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Message of the calling thread's latest error ("" if none). */
+const char* lbm_last_error(void);
+
+#pragma GCC visibility pop
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -1,0 +1,343 @@
+// abi.hip -- the extern "C" boundary declared in include/lbm.h: argument
+// validation on the host, context bookkeeping (which lattice holds f*(t)),
+// and dispatch to the kernel launchers.  Nothing here allocates device
+// memory or synchronises.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/lbm.h"
+#include "d3q19.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+lbm_status fail(lbm_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+lbm_status hip_fail(hipError_t e, const char* what) {
+  return fail(LBM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t elem_size(int32_t storage) {
+  switch (storage) {
+    case LBM_F32: return 4;
+    case LBM_F16: return 2;
+    case LBM_BF16: return 2;
+    case LBM_F64: return 8;
+    default: return 0;
+  }
+}
+
+bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+struct Sizes {
+  int64_t xs;
+  uint64_t plane;       // elements per direction array
+  size_t grid_bytes;
+  size_t scratch_bytes;
+  size_t adj_bytes;
+};
+
+lbm_status check_params(const lbm_params* p, Sizes* sz) {
+  if (!p) return fail(LBM_E_ARG, "params is NULL");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+    return fail(LBM_E_ARG, "grid dimensions must be >= 1 (got %d x %d x %d)", p->nx, p->ny, p->nz);
+  const size_t es = elem_size(p->storage);
+  if (!es) return fail(LBM_E_ARG, "unknown storage type %d", p->storage);
+  if (!(p->tau > 0.5) || std::isnan(p->tau) || (std::isinf(p->tau) && p->tau < 0))
+    return fail(LBM_E_ARG, "tau must be > 1/2 or +infinity (got %g)", p->tau);
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(p->force[d])) return fail(LBM_E_ARG, "force[%d] is not finite", d);
+  if (p->storage == LBM_F16 && (p->f16_scale_log2 < -24 || p->f16_scale_log2 > 24))
+    return fail(LBM_E_ARG, "f16_scale_log2 must be in [-24, 24] (got %d)", p->f16_scale_log2);
+  if (p->x_align < 0 || p->x_align > 4096)
+    return fail(LBM_E_ARG, "x_align must be in [0, 4096] (got %d)", p->x_align);
+  const int64_t align = p->x_align ? p->x_align : 64;
+  const int64_t xs = (int64_t(p->nx) + align - 1) / align * align;
+  const uint64_t plane = uint64_t(xs) * uint64_t(p->ny) * uint64_t(p->nz);
+  const uint64_t cells = uint64_t(p->nx) * uint64_t(p->ny) * uint64_t(p->nz);
+  if (plane * es > 0xFFFFFFFFull || cells >= (1ull << 31) || uint64_t(p->ny) * p->nz >= (1ull << 31))
+    return fail(LBM_E_UNSUPPORTED,
+                "grid too large: one direction array needs %llu bytes (limit 4 GiB - 1)",
+                (unsigned long long)(plane * es));
+  const lbm::Geo g = lbm::make_geo(p->nx, p->ny, p->nz, int(xs));
+  if (sz) {
+    sz->xs = xs;
+    sz->plane = plane;
+    sz->grid_bytes = (size_t(19) * plane * es + 255) / 256 * 256;
+    sz->scratch_bytes = size_t(lbm::kReduceBlocks) * 5 * sizeof(double);
+    sz->adj_bytes = size_t(g.nblocks) * 3 * sizeof(double);
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params p;
+  Sizes sz;
+  lbm::Geo geo;
+  lbm::PhysParams ph;
+  void* grid[2];
+  const uint8_t* flags;
+  double* scratch;
+  hipStream_t stream;
+  int32_t cur;
+  int64_t t;
+  bool force;
+};
+
+namespace {
+
+lbm_status check_ctx(const lbm_ctx* c) {
+  if (!c) return fail(LBM_E_ARG, "context is NULL");
+  return LBM_OK;
+}
+
+lbm_status launch_steps(lbm_ctx* c, const void* src, void* dst) {
+  hipError_t e = lbm::launch_step(c->p.storage, c->flags != nullptr, c->force, c->geo, c->ph, src,
+                                  dst, c->flags, c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "stream-collide launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_query(const lbm_params* p, int64_t* x_stride, size_t* grid_bytes,
+                     size_t* scratch_bytes, size_t* adj_partials_bytes) {
+  Sizes sz;
+  lbm_status st = check_params(p, &sz);
+  if (st != LBM_OK) return st;
+  if (x_stride) *x_stride = sz.xs;
+  if (grid_bytes) *grid_bytes = sz.grid_bytes;
+  if (scratch_bytes) *scratch_bytes = sz.scratch_bytes;
+  if (adj_partials_bytes) *adj_partials_bytes = sz.adj_bytes;
+  return LBM_OK;
+}
+
+int32_t lbm_bytes_per_update(int32_t storage) {
+  return int32_t(19 * 2 * elem_size(storage));
+}
+
+void lbm_lattice(int32_t* e, double* w, int32_t* opp) {
+  using lbm::D3Q19;
+  for (int i = 0; i < lbm::Q; ++i) {
+    if (e) {
+      e[3 * i + 0] = D3Q19::cx[i];
+      e[3 * i + 1] = D3Q19::cy[i];
+      e[3 * i + 2] = D3Q19::cz[i];
+    }
+    if (w) w[i] = lbm::weight<double>(i);
+    if (opp) opp[i] = D3Q19::opp[i];
+  }
+}
+
+lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* grid_a, void* grid_b,
+                    const uint8_t* flags, void* scratch, const float* rho0, const float* u0,
+                    void* stream) {
+  if (!out) return fail(LBM_E_ARG, "out is NULL");
+  *out = nullptr;
+  Sizes sz;
+  lbm_status st = check_params(p, &sz);
+  if (st != LBM_OK) return st;
+  if (!grid_a || !grid_b) return fail(LBM_E_ARG, "grid pointers must not be NULL");
+  if (grid_a == grid_b) return fail(LBM_E_ARG, "grid_a and grid_b must differ");
+  if (!scratch) return fail(LBM_E_ARG, "scratch must not be NULL");
+  if (!aligned256(grid_a) || !aligned256(grid_b) || !aligned256(scratch))
+    return fail(LBM_E_ARG, "grids and scratch must be 256-byte aligned");
+  if ((rho0 && (reinterpret_cast<uintptr_t>(rho0) & 3u)) ||
+      (u0 && (reinterpret_cast<uintptr_t>(u0) & 3u)))
+    return fail(LBM_E_ARG, "rho0 and u0 must be 4-byte aligned");
+  lbm_ctx* c = new (std::nothrow) lbm_ctx;
+  if (!c) return fail(LBM_E_ARG, "out of host memory");
+  c->p = *p;
+  c->sz = sz;
+  c->geo = lbm::make_geo(p->nx, p->ny, p->nz, int(sz.xs));
+  c->ph.omega = std::isinf(p->tau) ? 0.0 : 1.0 / p->tau;
+  for (int d = 0; d < 3; ++d) c->ph.F[d] = p->force[d];
+  c->ph.scale = p->storage == LBM_F16 ? std::ldexp(1.0, p->f16_scale_log2) : 1.0;
+  c->grid[0] = grid_a;
+  c->grid[1] = grid_b;
+  c->flags = flags;
+  c->scratch = static_cast<double*>(scratch);
+  c->stream = static_cast<hipStream_t>(stream);
+  c->cur = 0;
+  c->t = 0;
+  c->force = p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0;
+  hipError_t e = lbm::launch_fill_zero(grid_a, sz.grid_bytes, c->stream);
+  if (e == hipSuccess) e = lbm::launch_fill_zero(grid_b, sz.grid_bytes, c->stream);
+  if (e == hipSuccess)
+    e = lbm::launch_init(p->storage, c->geo, c->ph, grid_a, flags, rho0, u0, c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "initialisation launch");
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int32_t n) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (n < 0) return fail(LBM_E_ARG, "step count must be >= 0 (got %d)", n);
+  for (int32_t k = 0; k < n; ++k) {
+    st = launch_steps(c, c->grid[c->cur], c->grid[c->cur ^ 1]);
+    if (st != LBM_OK) return st;
+    c->cur ^= 1;
+    c->t += 1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_step_from(lbm_ctx* c, const void* src, void* dst) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!src || !dst) return fail(LBM_E_ARG, "src and dst must not be NULL");
+  if (src == dst) return fail(LBM_E_ARG, "src and dst must differ");
+  if (!aligned256(src) || !aligned256(dst)) return fail(LBM_E_ARG, "src/dst must be 256-byte aligned");
+  return launch_steps(c, src, dst);
+}
+
+static lbm_status macro_any(lbm_ctx* c, void* rho, void* u, bool f64) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!rho && !u) return LBM_OK;
+  hipError_t e = lbm::launch_macro(c->p.storage, f64, c->geo, c->ph, c->grid[c->cur], c->flags,
+                                   rho, u, c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "macroscopics launch");
+}
+
+lbm_status lbm_macroscopics(lbm_ctx* c, float* rho, float* u) { return macro_any(c, rho, u, false); }
+
+lbm_status lbm_macroscopics_f64(lbm_ctx* c, double* rho, double* u) {
+  return macro_any(c, rho, u, true);
+}
+
+lbm_status lbm_reduce(lbm_ctx* c, double* out5) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!out5) return fail(LBM_E_ARG, "out5 is NULL");
+  hipError_t e = lbm::launch_reduce(c->p.storage, c->geo, c->ph, c->grid[c->cur], c->flags,
+                                    c->scratch, out5, c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "reduction launch");
+}
+
+int32_t lbm_current(const lbm_ctx* c) { return c ? c->cur : -1; }
+int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+lbm_status lbm_set_current(lbm_ctx* c, int32_t parity, int64_t t) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (parity != 0 && parity != 1) return fail(LBM_E_ARG, "parity must be 0 or 1");
+  if (t < 0) return fail(LBM_E_ARG, "time must be >= 0");
+  c->cur = parity;
+  c->t = t;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_stream(lbm_ctx* c, void* stream) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  c->stream = static_cast<hipStream_t>(stream);
+  return LBM_OK;
+}
+
+lbm_status lbm_save(lbm_ctx* c, void* dst) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!dst) return fail(LBM_E_ARG, "dst is NULL");
+  hipError_t e = hipMemcpyAsync(dst, c->grid[c->cur], c->sz.grid_bytes, hipMemcpyDeviceToDevice,
+                                c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "save copy");
+}
+
+lbm_status lbm_restore(lbm_ctx* c, const void* src, int64_t t) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!src) return fail(LBM_E_ARG, "src is NULL");
+  if (t < 0) return fail(LBM_E_ARG, "time must be >= 0");
+  hipError_t e = hipMemcpyAsync(c->grid[c->cur], src, c->sz.grid_bytes, hipMemcpyDeviceToDevice,
+                                c->stream);
+  if (e != hipSuccess) return hip_fail(e, "restore copy");
+  c->t = t;
+  return LBM_OK;
+}
+
+static lbm_status adj_check(lbm_ctx* c) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (c->p.storage != LBM_F32)
+    return fail(LBM_E_UNSUPPORTED, "the adjoint supports FP32 storage only");
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_seed(lbm_ctx* c, const float* dL_drho, const float* dL_du, float* lam_T,
+                            double* partials) {
+  lbm_status st = adj_check(c);
+  if (st != LBM_OK) return st;
+  if (!lam_T || !partials) return fail(LBM_E_ARG, "lam_T and partials must not be NULL");
+  if (!aligned256(lam_T)) return fail(LBM_E_ARG, "lam_T must be 256-byte aligned");
+  hipError_t e = lbm::launch_adj_seed(c->geo, c->ph, static_cast<const float*>(c->grid[c->cur]),
+                                      c->flags, dL_drho, dL_du, lam_T, partials, c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint seed launch");
+}
+
+lbm_status lbm_adjoint_step(lbm_ctx* c, const void* fstar_n, const float* lam_np1, float* lam_n,
+                            double* partials) {
+  lbm_status st = adj_check(c);
+  if (st != LBM_OK) return st;
+  if (!fstar_n || !lam_np1 || !lam_n || !partials)
+    return fail(LBM_E_ARG, "adjoint step pointers must not be NULL");
+  if (lam_np1 == lam_n) return fail(LBM_E_ARG, "lam_np1 and lam_n must differ");
+  if (!aligned256(fstar_n) || !aligned256(lam_np1) || !aligned256(lam_n))
+    return fail(LBM_E_ARG, "adjoint grids must be 256-byte aligned");
+  hipError_t e = lbm::launch_adj_step(c->flags != nullptr, c->geo, c->ph,
+                                      static_cast<const float*>(fstar_n), c->flags, lam_np1, lam_n,
+                                      partials, c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint step launch");
+}
+
+lbm_status lbm_adjoint_init(lbm_ctx* c, const float* lam_0, const float* rho0, const float* u0,
+                            float* dL_du0) {
+  lbm_status st = adj_check(c);
+  if (st != LBM_OK) return st;
+  if (!lam_0 || !dL_du0) return fail(LBM_E_ARG, "lam_0 and dL_du0 must not be NULL");
+  hipError_t e = lbm::launch_adj_init(c->geo, c->flags, lam_0, rho0, u0, dL_du0, c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint init launch");
+}
+
+lbm_status lbm_adjoint_finish_dF(lbm_ctx* c, const double* partials, double* dLdF3) {
+  lbm_status st = adj_check(c);
+  if (st != LBM_OK) return st;
+  if (!partials || !dLdF3) return fail(LBM_E_ARG, "partials and dLdF3 must not be NULL");
+  hipError_t e = lbm::launch_adj_finish(c->geo, partials, dLdF3, c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint finish launch");
+}
+
+lbm_status lbm_stream_copy(void* dst, const void* src, size_t n_bytes, void* stream) {
+  if (!dst || !src) return fail(LBM_E_ARG, "copy pointers must not be NULL");
+  if (!aligned256(dst) || !aligned256(src)) return fail(LBM_E_ARG, "copy pointers must be 256-byte aligned");
+  if (n_bytes % 16) return fail(LBM_E_ARG, "n_bytes must be a multiple of 16");
+  if (!n_bytes) return LBM_OK;
+  hipError_t e = lbm::launch_copy(dst, src, n_bytes / 16, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "copy launch");
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+const char* lbm_last_error(void) { return g_err; }
+
+}  // extern "C"

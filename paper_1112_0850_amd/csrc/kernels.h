@@ -1,0 +1,56 @@
+// kernels.h -- launch interface between the C ABI glue and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Launch geometry shared by every per-cell kernel.  A wavefront owns a
+// 64-cell segment of one x-row; a 256-thread block owns 4 consecutive
+// segments in (z, y, segment) order.  Blocks are remapped so that each of
+// the 8 XCDs (which receive hardware block ids round-robin) works on one
+// contiguous eighth of the domain, keeping neighbouring rows in one L2.
+struct Geo {
+  int32_t nx, ny, nz;
+  int32_t xs;       // x stride of a population row, in cells
+  uint32_t plane;   // elements of one direction array: nz * ny * xs
+  int32_t nseg;     // 64-cell segments per row
+  int32_t nrows;    // ny * nz
+  int32_t nblocks;  // blocks launched (4 segments each)
+  int32_t nb8;      // nblocks rounded down to a multiple of 8
+};
+
+constexpr int kBlock = 256;
+constexpr int kReduceBlocks = 1024;
+
+struct PhysParams {
+  double omega;     // 1 / tau (0 for tau = +inf)
+  double F[3];      // body-force density
+  double scale;     // FP16 storage scale 2^s (1 otherwise)
+};
+
+Geo make_geo(int nx, int ny, int nz, int xs);
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_init(int storage, const Geo& g, const PhysParams& ph, void* grid,
+                       const uint8_t* flags, const float* rho0, const float* u0, hipStream_t s);
+hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
+                       const void* src, void* dst, const uint8_t* flags, hipStream_t s);
+hipError_t launch_macro(int storage, bool out_f64, const Geo& g, const PhysParams& ph,
+                        const void* grid, const uint8_t* flags, void* rho, void* u, hipStream_t s);
+hipError_t launch_reduce(int storage, const Geo& g, const PhysParams& ph, const void* grid,
+                         const uint8_t* flags, double* scratch, double* out5, hipStream_t s);
+hipError_t launch_adj_seed(const Geo& g, const PhysParams& ph, const float* fT, const uint8_t* flags,
+                           const float* dL_drho, const float* dL_du, float* lam, double* partials,
+                           hipStream_t s);
+hipError_t launch_adj_step(bool solids, const Geo& g, const PhysParams& ph, const float* fn,
+                           const uint8_t* flags, const float* lam_np1, float* lam_n,
+                           double* partials, hipStream_t s);
+hipError_t launch_adj_init(const Geo& g, const uint8_t* flags, const float* lam0, const float* rho0,
+                           const float* u0, float* dL_du0, hipStream_t s);
+hipError_t launch_adj_finish(const Geo& g, const double* partials, double* out3, hipStream_t s);
+hipError_t launch_copy(void* c, const void* a, size_t n16, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,788 @@
+// kernels.hip -- gfx950 kernels of the D3Q19 BGK hot path.
+//
+// One thread updates one cell (Sec. 6: a single thread computes the update
+// of a single lattice node).  The fused kernel follows the paper's
+// stream-collide ("pull") ordering: it gathers the 19 post-collision values
+// of the previous step from the neighbours x - c_i (Sec. 2 step 3, with
+// half-way bounce-back at solid neighbours), computes the moments and the
+// equilibrium and relaxes (Sec. 2 steps 1-2, Eq. (1)), adds the Guo forcing
+// term, and writes the 19 results to its own cell of the second lattice
+// (aligned, coalesced stores).  Populations are structure-of-arrays with x
+// contiguous, so each of the 19 gathers of a wavefront is one contiguous
+// 64-element run shifted by at most one element.
+//
+// All population values are offsets g = f - w (rest state = 0), which keeps
+// FP32/FP16/BF16 storage free of the f ~ w cancellation.  In offset form,
+// with delta_rho = sum g_i, j = sum g_i c_i and j' = j + F/2 = rho u,
+//   u = j'/(1 + delta_rho),
+//   g^eq_i = w_i [delta_rho + rho (3 c_i.u + 9/2 (c_i.u)^2 - 3/2 u.u)]
+//          = w_i (delta_rho - 3/2 j'.u) + 9/2 w_i (c_i.j')(c_i.u) + 3 w_i (c_i.j'),
+//   S_i = (1 - omega/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F       (Guo 2002),
+//   g*_i = (1 - omega) g_i + omega g^eq_i + S_i.
+// The second form of g^eq never rounds rho = 1 + delta_rho (see collide()).
+#include "d3q19.h"
+#include "kernels.h"
+
+namespace lbm {
+
+Geo make_geo(int nx, int ny, int nz, int xs) {
+  Geo g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.xs = xs;
+  g.plane = uint32_t(uint64_t(nz) * uint64_t(ny) * uint64_t(xs));
+  g.nseg = (nx + 63) / 64;
+  g.nrows = ny * nz;
+  const int64_t segs = int64_t(g.nseg) * g.nrows;
+  g.nblocks = int32_t((segs + 3) / 4);
+  g.nb8 = (g.nblocks / 8) * 8;
+  return g;
+}
+
+template <typename C>
+struct Phys {
+  C omega;
+  C F[3];
+  C scale;
+  C inv_scale;
+};
+
+template <typename C>
+static Phys<C> to_phys(const PhysParams& p) {
+  Phys<C> r;
+  r.omega = C(p.omega);
+  for (int d = 0; d < 3; ++d) r.F[d] = C(p.F[d]);
+  r.scale = C(p.scale);
+  r.inv_scale = C(1.0 / p.scale);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Thread -> cell mapping.
+// ---------------------------------------------------------------------------
+struct Loc {
+  int x, y, z;
+  int lblock;  // logical block id after the XCD remap
+  bool valid;
+};
+
+__device__ __forceinline__ Loc locate(const Geo& g) {
+  Loc l;
+  const int b = blockIdx.x;
+  // Hardware hands block b to XCD b % 8; give XCD k the k-th contiguous
+  // eighth of the logical blocks (the tail beyond nb8 maps to itself).
+  const int lb = (b < g.nb8) ? ((b & 7) * (g.nb8 >> 3) + (b >> 3)) : b;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int seg = lb * 4 + wave;
+  const int row = seg / g.nseg;
+  l.x = (seg - row * g.nseg) * 64 + int(threadIdx.x & 63);
+  l.z = row / g.ny;
+  l.y = row - l.z * g.ny;
+  l.lblock = lb;
+  l.valid = (row < g.nrows) && (l.x < g.nx);
+  return l;
+}
+
+// Offsets of the 3x3 neighbouring rows (periodic) and of the x-neighbours.
+struct Nbhd {
+  uint32_t row[3][3];   // [dz+1][dy+1]: element offset of row (y+dy, z+dz) in one direction array
+  uint32_t frow[3][3];  // same row in the unpadded cell numbering (flags, fields)
+  uint32_t xn[3];       // [cx+1]: the x of the pull source x - cx
+  uint32_t own, fown;
+};
+
+__device__ __forceinline__ Nbhd neighbourhood(const Geo& g, const Loc& l) {
+  Nbhd n;
+  const int ys[3] = {l.y == 0 ? g.ny - 1 : l.y - 1, l.y, l.y + 1 == g.ny ? 0 : l.y + 1};
+  const int zs[3] = {l.z == 0 ? g.nz - 1 : l.z - 1, l.z, l.z + 1 == g.nz ? 0 : l.z + 1};
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      const uint32_t r = uint32_t(zs[dz] * g.ny + ys[dy]);
+      n.row[dz][dy] = r * uint32_t(g.xs);
+      n.frow[dz][dy] = r * uint32_t(g.nx);
+    }
+  n.xn[0] = (l.x + 1 == g.nx) ? 0u : uint32_t(l.x + 1);
+  n.xn[1] = uint32_t(l.x);
+  n.xn[2] = (l.x == 0) ? uint32_t(g.nx - 1) : uint32_t(l.x - 1);
+  n.own = n.row[1][1] + uint32_t(l.x);
+  n.fown = n.frow[1][1] + uint32_t(l.x);
+  return n;
+}
+
+// Offset of the pull source x - c_i of direction i (compile-time i).
+__device__ __forceinline__ uint32_t src_off(const Nbhd& n, int i) {
+  return n.row[1 - D3Q19::cz[i]][1 - D3Q19::cy[i]] + n.xn[D3Q19::cx[i] + 1];
+}
+__device__ __forceinline__ uint32_t src_foff(const Nbhd& n, int i) {
+  return n.frow[1 - D3Q19::cz[i]][1 - D3Q19::cy[i]] + n.xn[D3Q19::cx[i] + 1];
+}
+
+// c_i . (x, y, z) without multiplications by the constant components (the
+// -0.0 start folds away exactly under IEEE rules).
+template <typename C>
+__device__ __forceinline__ C cdot(int i, C x, C y, C z) {
+  C r = C(-0.0);
+  r = D3Q19::cx[i] > 0 ? r + x : (D3Q19::cx[i] < 0 ? r - x : r);
+  r = D3Q19::cy[i] > 0 ? r + y : (D3Q19::cy[i] < 0 ? r - y : r);
+  r = D3Q19::cz[i] > 0 ? r + z : (D3Q19::cz[i] < 0 ? r - z : r);
+  return r;
+}
+
+// Pull streaming with half-way bounce-back: f_i(x) = f*_i(x - c_i) when that
+// cell is fluid, else f*_{opp i}(x).
+template <int K, bool SOLIDS>
+__device__ __forceinline__ void pull(const typename Storage<K>::T* __restrict__ src,
+                                     const uint8_t* __restrict__ flags, const Geo& g,
+                                     const Nbhd& n, typename Storage<K>::C inv_scale,
+                                     typename Storage<K>::C* f) {
+  using T = typename Storage<K>::T;
+  bool bb[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    bb[i] = SOLIDS && i != 0 && (flags[src_foff(n, i)] & FLAG_SOLID);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const T* p = src + size_t(i) * g.plane + src_off(n, i);
+    if (SOLIDS && i != 0) {
+      const T* q = src + size_t(D3Q19::opp[i]) * g.plane + n.own;
+      p = bb[i] ? q : p;
+    }
+    f[i] = Storage<K>::load(*p, inv_scale);
+  }
+}
+
+// Moments of an offset population set: delta_rho and j.
+template <typename C>
+__device__ __forceinline__ void moments(const C* f, C& drho, C& jx, C& jy, C& jz) {
+  drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) +
+         ((f[8] + f[9]) + (f[10] + f[11])) + ((f[12] + f[13]) + (f[14] + f[15])) +
+         ((f[16] + f[17]) + f[18]);
+  jx = ((f[1] - f[2]) + (f[7] - f[8])) + ((f[9] - f[10]) + (f[11] - f[12])) + (f[13] - f[14]);
+  jy = ((f[3] - f[4]) + (f[7] - f[8])) + ((f[10] - f[9]) + (f[15] - f[16])) + (f[17] - f[18]);
+  jz = ((f[5] - f[6]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16])) + (f[18] - f[17]);
+}
+
+// u from j' = rho u and delta_rho without rounding rho = 1 + delta_rho:
+// u = j' / (1 + drho) = j' - j' t,  t = drho / (1 + drho).  (Near rho = 1 a
+// rounded rho carries an error that is a smooth function of the field and
+// accumulates coherently; j' - j' t is accurate to the rounding of u.)
+template <typename C>
+__device__ __forceinline__ C inv_rho_factor(C drho) {
+  return drho / (C(1) + drho);
+}
+
+// BGK relaxation towards the Qian equilibrium with Guo forcing, in place.
+// Offset form with rho never formed:  j' = j + F/2 = rho u,
+//   g^eq_i = W_i (drho - 3/2 j'.u) + c_i (c_i.j')(c_i.u) +- a_i (c_i.j')
+// (coefficients in Coef<C>), g*_i = (1 - omega) g_i + omega g^eq_i + S_i.
+template <typename C, bool FORCE>
+__device__ __forceinline__ void collide(C* f, C omega, C Fx, C Fy, C Fz) {
+  C drho, jx, jy, jz;
+  moments(f, drho, jx, jy, jz);
+  if (FORCE) {
+    jx += C(0.5) * Fx;
+    jy += C(0.5) * Fy;
+    jz += C(0.5) * Fz;
+  }
+  const C t = inv_rho_factor(drho);
+  const C ux = jx - jx * t, uy = jy - jy * t, uz = jz - jz * t;
+  const C base = drho - C(1.5) * (jx * ux + jy * uy + jz * uz);
+  const C om1 = C(1) - omega;
+  const C fpre = C(1) - C(0.5) * omega;
+  const C uF = FORCE ? (ux * Fx + uy * Fy + uz * Fz) : C(0);
+  {
+    C v = om1 * f[0] + omega * (coef_W<C>(0) * base);
+    if (FORCE) v += fpre * (C(-3) * coef_W<C>(0) * uF);
+    f[0] = v;
+  }
+#pragma unroll
+  for (int k = 1; k < Q; k += 2) {  // pair (k, k+1) = (c, -c)
+    const C ej = cdot<C>(k, jx, jy, jz);
+    const C eu = cdot<C>(k, ux, uy, uz);
+    const C sym = coef_W<C>(k) * base + coef_c<C>(k) * ej * eu;
+    const C anti = coef_a<C>(k) * ej;
+    C a = om1 * f[k] + omega * (sym + anti);
+    C b = om1 * f[k + 1] + omega * (sym - anti);
+    if (FORCE) {
+      const C cF = cdot<C>(k, Fx, Fy, Fz);
+      const C ssym = fpre * (coef_q<C>(k) * eu * cF - C(3) * coef_W<C>(k) * uF);
+      const C santi = fpre * (coef_a<C>(k) * cF);
+      a += ssym + santi;
+      b += ssym - santi;
+    }
+    f[k] = a;
+    f[k + 1] = b;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused stream-collide step.
+// ---------------------------------------------------------------------------
+template <int K, bool SOLIDS, bool FORCE>
+__global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* __restrict__ src,
+                                                 typename Storage<K>::T* __restrict__ dst,
+                                                 const uint8_t* __restrict__ flags, Geo g,
+                                                 Phys<typename Storage<K>::C> ph) {
+  using C = typename Storage<K>::C;
+  const Loc l = locate(g);
+  if (!l.valid) return;
+  const Nbhd n = neighbourhood(g, l);
+  uint8_t own = 0;
+  if (SOLIDS) {
+    own = flags[n.fown];
+    if (own & FLAG_SOLID) return;  // obstacle cells are never read or written
+  }
+  C f[Q];
+  pull<K, SOLIDS>(src, flags, g, n, ph.inv_scale, f);
+  C Fx = ph.F[0], Fy = ph.F[1], Fz = ph.F[2];
+  if (SOLIDS && FORCE && (own & FLAG_NOFORCE)) Fx = Fy = Fz = C(0);
+  collide<C, FORCE>(f, ph.omega, Fx, Fy, Fz);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) dst[size_t(i) * g.plane + n.own] = Storage<K>::store(f[i], ph.scale);
+}
+
+// ---------------------------------------------------------------------------
+// Initial state f*(0) = f^eq(rho0, u0), written as offsets.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_init(typename Storage<K>::T* __restrict__ grid,
+                                                 const uint8_t* __restrict__ flags,
+                                                 const float* __restrict__ rho0,
+                                                 const float* __restrict__ u0, Geo g,
+                                                 Phys<typename Storage<K>::C> ph) {
+  using C = typename Storage<K>::C;
+  const Loc l = locate(g);
+  if (!l.valid) return;
+  const uint32_t c = uint32_t((l.z * g.ny + l.y) * g.nx + l.x);
+  if (flags && (flags[c] & FLAG_SOLID)) return;
+  const size_t ncell = size_t(g.nx) * g.ny * g.nz;
+  const uint32_t own = uint32_t(l.z * g.ny + l.y) * uint32_t(g.xs) + uint32_t(l.x);
+  const C rho = rho0 ? C(rho0[c]) : C(1);
+  C ux = C(0), uy = C(0), uz = C(0);
+  if (u0) {
+    ux = C(u0[c]);
+    uy = C(u0[ncell + c]);
+    uz = C(u0[2 * ncell + c]);
+  }
+  // f^eq(rho0, u0) - w in the collision's coefficient form, j' = rho0 u0.
+  const C drho = rho - C(1);
+  const C jx = rho * ux, jy = rho * uy, jz = rho * uz;
+  const C base = drho - C(1.5) * (jx * ux + jy * uy + jz * uz);
+  grid[own] = Storage<K>::store(coef_W<C>(0) * base, ph.scale);
+#pragma unroll
+  for (int k = 1; k < Q; k += 2) {
+    const C ej = cdot<C>(k, jx, jy, jz);
+    const C eu = cdot<C>(k, ux, uy, uz);
+    const C sym = coef_W<C>(k) * base + coef_c<C>(k) * ej * eu;
+    const C anti = coef_a<C>(k) * ej;
+    grid[size_t(k) * g.plane + own] = Storage<K>::store(sym + anti, ph.scale);
+    grid[size_t(k + 1) * g.plane + own] = Storage<K>::store(sym - anti, ph.scale);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Macroscopic fields from the stored post-collision state:
+// rho = 1 + sum g*_i, rho u = sum g*_i c_i - F/2.
+// ---------------------------------------------------------------------------
+template <int K, typename O>
+__global__ __launch_bounds__(kBlock) void k_macro(const typename Storage<K>::T* __restrict__ grid,
+                                                  const uint8_t* __restrict__ flags,
+                                                  O* __restrict__ rho_out, O* __restrict__ u_out,
+                                                  Geo g, O Fx, O Fy, O Fz, O inv_scale) {
+  const Loc l = locate(g);
+  if (!l.valid) return;
+  const uint32_t c = uint32_t((l.z * g.ny + l.y) * g.nx + l.x);
+  const size_t ncell = size_t(g.nx) * g.ny * g.nz;
+  const uint32_t own = uint32_t(l.z * g.ny + l.y) * uint32_t(g.xs) + uint32_t(l.x);
+  const uint8_t fl = flags ? flags[c] : uint8_t(0);
+  O r = O(0), ux = O(0), uy = O(0), uz = O(0);
+  if (!(fl & FLAG_SOLID)) {
+    O f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      f[i] = O(Storage<K>::load(grid[size_t(i) * g.plane + own],
+                                typename Storage<K>::C(inv_scale)));
+    O drho, jx, jy, jz;
+    moments(f, drho, jx, jy, jz);
+    if (fl & FLAG_NOFORCE) Fx = Fy = Fz = O(0);
+    r = O(1) + drho;
+    const O t = inv_rho_factor(drho);
+    const O mx = jx - O(0.5) * Fx, my = jy - O(0.5) * Fy, mz = jz - O(0.5) * Fz;
+    ux = mx - mx * t;
+    uy = my - my * t;
+    uz = mz - mz * t;
+  }
+  if (rho_out) rho_out[c] = r;
+  if (u_out) {
+    u_out[c] = ux;
+    u_out[ncell + c] = uy;
+    u_out[2 * ncell + c] = uz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions: per-block partials (fixed cell -> thread assignment and a
+// fixed LDS tree), then one block sums the partials in a fixed order.
+// ---------------------------------------------------------------------------
+template <int NC>
+__device__ __forceinline__ void block_sum(double (&v)[NC], double* sh) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) sh[k * kBlock + t] = v[k];
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    __syncthreads();
+    if (t < s) {
+#pragma unroll
+      for (int k = 0; k < NC; ++k) sh[k * kBlock + t] += sh[k * kBlock + t + s];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NC; ++k) v[k] = sh[k * kBlock];
+}
+
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_reduce_partials(const typename Storage<K>::T* __restrict__ grid,
+                                                            const uint8_t* __restrict__ flags, Geo g,
+                                                            double Fx, double Fy, double Fz,
+                                                            double inv_scale, double* __restrict__ out) {
+  __shared__ double sh[5 * kBlock];
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const int64_t ncell = int64_t(g.nx) * g.ny * g.nz;
+  for (int64_t c = int64_t(blockIdx.x) * kBlock + threadIdx.x; c < ncell;
+       c += int64_t(gridDim.x) * kBlock) {
+    const uint8_t fl = flags ? flags[c] : uint8_t(0);
+    if (fl & FLAG_SOLID) continue;
+    const int64_t row = c / g.nx;
+    const uint32_t own = uint32_t(row * g.xs + (c - row * g.nx));
+    double f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      f[i] = double(Storage<K>::load(grid[size_t(i) * g.plane + own],
+                                     typename Storage<K>::C(inv_scale)));
+    double drho, jx, jy, jz;
+    moments(f, drho, jx, jy, jz);
+    const double h = (fl & FLAG_NOFORCE) ? 0.0 : 0.5;
+    const double rho = 1.0 + drho;
+    const double px = jx - h * Fx, py = jy - h * Fy, pz = jz - h * Fz;
+    acc[0] += rho;
+    acc[1] += px;
+    acc[2] += py;
+    acc[3] += pz;
+    acc[4] += 0.5 * (px * px + py * py + pz * pz) / rho;
+  }
+  block_sum<5>(acc, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 5; ++k) out[blockIdx.x * 5 + k] = acc[k];
+}
+
+// Sums nparts partial records of NC doubles each, in a fixed order.
+template <int NC>
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ parts, int nparts,
+                                                         double* __restrict__ out) {
+  __shared__ double sh[NC * kBlock];
+  double acc[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) acc[k] = 0.0;
+  for (int p = threadIdx.x; p < nparts; p += kBlock)
+#pragma unroll
+    for (int k = 0; k < NC; ++k) acc[k] += parts[size_t(p) * NC + k];
+  block_sum<NC>(acc, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NC; ++k) out[k] = acc[k];
+}
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint (FP32 storage).  With lambda = dL/d f* at a fluid cell and
+// the weighted moments of lambda
+//   L0 = sum w_i lam_i,  L1 = sum w_i lam_i c_i,  L2 = sum w_i lam_i c_i c_i^T,
+// the transposed collision Jacobian is rank-structured:
+//   a  = omega (L0 + 3 L1.u + 9/2 u.L2 u - 3/2 u.u L0)
+//   b  = omega rho (3 L1 + 9 L2 u - 3 u L0) + (1 - omega/2)(9 L2 F - 3 F L0)
+//   mu_j = (1 - omega) lam_j + a + b . (c_j - u) / rho
+//   dL/dF += (1 - omega/2)(3 L1 - 3 u L0 + 9 L2 u) + b / (2 rho)
+// ---------------------------------------------------------------------------
+struct LamMoments {
+  float L0, L1x, L1y, L1z, Lxx, Lyy, Lzz, Lxy, Lxz, Lyz;
+};
+
+__device__ __forceinline__ LamMoments lam_moments(const float* lam) {
+  LamMoments m;
+  m.L0 = m.L1x = m.L1y = m.L1z = -0.0f;
+  m.Lxx = m.Lyy = m.Lzz = m.Lxy = m.Lxz = m.Lyz = -0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float wl = weight<float>(i) * lam[i];
+    const int cx = D3Q19::cx[i], cy = D3Q19::cy[i], cz = D3Q19::cz[i];
+    m.L0 += wl;
+    if (cx) m.L1x += cx > 0 ? wl : -wl;
+    if (cy) m.L1y += cy > 0 ? wl : -wl;
+    if (cz) m.L1z += cz > 0 ? wl : -wl;
+    if (cx) m.Lxx += wl;
+    if (cy) m.Lyy += wl;
+    if (cz) m.Lzz += wl;
+    if (cx * cy) m.Lxy += cx * cy > 0 ? wl : -wl;
+    if (cx * cz) m.Lxz += cx * cz > 0 ? wl : -wl;
+    if (cy * cz) m.Lyz += cy * cz > 0 ? wl : -wl;
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_seed(const float* __restrict__ fT,
+                                                     const uint8_t* __restrict__ flags,
+                                                     const float* __restrict__ gr,
+                                                     const float* __restrict__ gu,
+                                                     float* __restrict__ lam,
+                                                     double* __restrict__ partials, Geo g,
+                                                     float Fx, float Fy, float Fz) {
+  __shared__ double sh[3 * kBlock];
+  double d[3] = {0.0, 0.0, 0.0};
+  const Loc l = locate(g);
+  if (l.valid) {
+    const uint32_t c = uint32_t((l.z * g.ny + l.y) * g.nx + l.x);
+    const size_t ncell = size_t(g.nx) * g.ny * g.nz;
+    const uint32_t own = uint32_t(l.z * g.ny + l.y) * uint32_t(g.xs) + uint32_t(l.x);
+    const uint8_t fl = flags ? flags[c] : uint8_t(0);
+    if (fl & FLAG_SOLID) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) lam[size_t(i) * g.plane + own] = 0.0f;
+    } else {
+      float f[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = fT[size_t(i) * g.plane + own];
+      float drho, jx, jy, jz;
+      moments(f, drho, jx, jy, jz);
+      const bool forced = !(fl & FLAG_NOFORCE);
+      const float h = forced ? 0.5f : 0.0f;
+      const float rho = 1.0f + drho;
+      const float ux = (jx - h * Fx) / rho, uy = (jy - h * Fy) / rho, uz = (jz - h * Fz) / rho;
+      const float G = gr ? gr[c] : 0.0f;
+      float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+      if (gu) {
+        gx = gu[c];
+        gy = gu[ncell + c];
+        gz = gu[2 * ncell + c];
+      }
+      const float hx = gx / rho, hy = gy / rho, hz = gz / rho;
+      const float base = G - (hx * ux + hy * uy + hz * uz);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) lam[size_t(i) * g.plane + own] = base + cdot<float>(i, hx, hy, hz);
+      if (forced) {
+        d[0] = -double(gx) / (2.0 * double(rho));
+        d[1] = -double(gy) / (2.0 * double(rho));
+        d[2] = -double(gz) / (2.0 * double(rho));
+      }
+    }
+  }
+  block_sum<3>(d, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) partials[size_t(l.lblock) * 3 + k] = d[k];
+}
+
+template <bool SOLIDS>
+__global__ __launch_bounds__(kBlock) void k_adj_step(const float* __restrict__ fn,
+                                                     const uint8_t* __restrict__ flags,
+                                                     const float* __restrict__ lam1,
+                                                     float* __restrict__ lam0,
+                                                     double* __restrict__ partials, Geo g,
+                                                     Phys<float> ph) {
+  __shared__ double sh[3 * kBlock];
+  double d[3] = {0.0, 0.0, 0.0};
+  const Loc l = locate(g);
+  if (l.valid) {
+    const Nbhd n = neighbourhood(g, l);
+    const uint8_t fl = SOLIDS ? flags[n.fown] : uint8_t(0);
+    if (!(fl & FLAG_SOLID)) {
+      bool bb[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        bb[i] = SOLIDS && i != 0 && (flags[src_foff(n, i)] & FLAG_SOLID);
+      // recompute the pre-collision state f(n+1) = stream(f*(n))
+      float f[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const float* p = fn + size_t(i) * g.plane + src_off(n, i);
+        if (SOLIDS && i != 0) p = bb[i] ? fn + size_t(D3Q19::opp[i]) * g.plane + n.own : p;
+        f[i] = *p;
+      }
+      float lam[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) lam[i] = lam1[size_t(i) * g.plane + n.own];
+      const bool forced = !(fl & FLAG_NOFORCE);
+      const float Fx = forced ? ph.F[0] : 0.0f, Fy = forced ? ph.F[1] : 0.0f,
+                  Fz = forced ? ph.F[2] : 0.0f;
+      float drho, jx, jy, jz;
+      moments(f, drho, jx, jy, jz);
+      const float rho = 1.0f + drho;
+      const float inv_rho = 1.0f / rho;
+      const float ux = (jx + 0.5f * Fx) * inv_rho, uy = (jy + 0.5f * Fy) * inv_rho,
+                  uz = (jz + 0.5f * Fz) * inv_rho;
+      const float om = ph.omega, om1 = 1.0f - om, fpre = 1.0f - 0.5f * om;
+      const LamMoments m = lam_moments(lam);
+      // L2 u and L2 F
+      const float Lux = m.Lxx * ux + m.Lxy * uy + m.Lxz * uz;
+      const float Luy = m.Lxy * ux + m.Lyy * uy + m.Lyz * uz;
+      const float Luz = m.Lxz * ux + m.Lyz * uy + m.Lzz * uz;
+      const float LFx = m.Lxx * Fx + m.Lxy * Fy + m.Lxz * Fz;
+      const float LFy = m.Lxy * Fx + m.Lyy * Fy + m.Lyz * Fz;
+      const float LFz = m.Lxz * Fx + m.Lyz * Fy + m.Lzz * Fz;
+      const float uu = ux * ux + uy * uy + uz * uz;
+      const float a = om * (m.L0 + 3.0f * (m.L1x * ux + m.L1y * uy + m.L1z * uz) +
+                            4.5f * (ux * Lux + uy * Luy + uz * Luz) - 1.5f * uu * m.L0);
+      const float orho = om * rho;
+      const float bx = orho * (3.0f * m.L1x + 9.0f * Lux - 3.0f * ux * m.L0) +
+                       fpre * (9.0f * LFx - 3.0f * Fx * m.L0);
+      const float by = orho * (3.0f * m.L1y + 9.0f * Luy - 3.0f * uy * m.L0) +
+                       fpre * (9.0f * LFy - 3.0f * Fy * m.L0);
+      const float bz = orho * (3.0f * m.L1z + 9.0f * Luz - 3.0f * uz * m.L0) +
+                       fpre * (9.0f * LFz - 3.0f * Fz * m.L0);
+      const float bhx = bx * inv_rho, bhy = by * inv_rho, bhz = bz * inv_rho;
+      const float a0 = a - (bhx * ux + bhy * uy + bhz * uz);
+      // transposed streaming: push mu_i to the pull source of direction i
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const float mu = om1 * lam[i] + a0 + cdot<float>(i, bhx, bhy, bhz);
+        float* p = lam0 + size_t(i) * g.plane + src_off(n, i);
+        if (SOLIDS && i != 0) p = bb[i] ? lam0 + size_t(D3Q19::opp[i]) * g.plane + n.own : p;
+        *p = mu;
+      }
+      if (forced) {
+        d[0] = double(fpre * (3.0f * m.L1x - 3.0f * ux * m.L0 + 9.0f * Lux) + 0.5f * bhx);
+        d[1] = double(fpre * (3.0f * m.L1y - 3.0f * uy * m.L0 + 9.0f * Luy) + 0.5f * bhy);
+        d[2] = double(fpre * (3.0f * m.L1z - 3.0f * uz * m.L0 + 9.0f * Luz) + 0.5f * bhz);
+      }
+    }
+  }
+  block_sum<3>(d, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) partials[size_t(l.lblock) * 3 + k] += d[k];
+}
+
+// dL/du0 = sum_i lam0_i w_i rho0 (3 c_i + 9 (c_i.u0) c_i - 3 u0) = rho0 (3 L1 + 9 L2 u0 - 3 u0 L0).
+__global__ __launch_bounds__(kBlock) void k_adj_init(const float* __restrict__ lam0,
+                                                     const uint8_t* __restrict__ flags,
+                                                     const float* __restrict__ rho0,
+                                                     const float* __restrict__ u0,
+                                                     float* __restrict__ du0, Geo g) {
+  const Loc l = locate(g);
+  if (!l.valid) return;
+  const uint32_t c = uint32_t((l.z * g.ny + l.y) * g.nx + l.x);
+  const size_t ncell = size_t(g.nx) * g.ny * g.nz;
+  const uint32_t own = uint32_t(l.z * g.ny + l.y) * uint32_t(g.xs) + uint32_t(l.x);
+  float rx = 0.0f, ry = 0.0f, rz = 0.0f;
+  if (!(flags && (flags[c] & FLAG_SOLID))) {
+    float lam[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lam[i] = lam0[size_t(i) * g.plane + own];
+    const LamMoments m = lam_moments(lam);
+    const float rho = rho0 ? rho0[c] : 1.0f;
+    float ux = 0.0f, uy = 0.0f, uz = 0.0f;
+    if (u0) {
+      ux = u0[c];
+      uy = u0[ncell + c];
+      uz = u0[2 * ncell + c];
+    }
+    const float Lux = m.Lxx * ux + m.Lxy * uy + m.Lxz * uz;
+    const float Luy = m.Lxy * ux + m.Lyy * uy + m.Lyz * uz;
+    const float Luz = m.Lxz * ux + m.Lyz * uy + m.Lzz * uz;
+    rx = rho * (3.0f * m.L1x + 9.0f * Lux - 3.0f * ux * m.L0);
+    ry = rho * (3.0f * m.L1y + 9.0f * Luy - 3.0f * uy * m.L0);
+    rz = rho * (3.0f * m.L1z + 9.0f * Luz - 3.0f * uz * m.L0);
+  }
+  du0[c] = rx;
+  du0[ncell + c] = ry;
+  du0[2 * ncell + c] = rz;
+}
+
+// ---------------------------------------------------------------------------
+// Utility kernels.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_fill_zero(uint4* __restrict__ p, size_t n16) {
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  for (size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x; i < n16; i += size_t(gridDim.x) * kBlock)
+    p[i] = z;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_zero_bytes(uint8_t* __restrict__ p, size_t n) {
+  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// STREAM copy c = a: four 16-byte elements per thread, coalesced.
+__global__ __launch_bounds__(kBlock) void k_copy(uint4* __restrict__ c, const uint4* __restrict__ a,
+                                                 size_t n16) {
+  const size_t base = size_t(blockIdx.x) * (kBlock * 4) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const size_t i = base + size_t(k) * kBlock;
+    if (i < n16) c[i] = a[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  const size_t n16 = bytes / 16;
+  if (n16) {
+    size_t blocks = (n16 + kBlock - 1) / kBlock;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill_zero, dim3(unsigned(blocks)), dim3(kBlock), 0, s,
+                       reinterpret_cast<uint4*>(p), n16);
+  }
+  const size_t tail = bytes - n16 * 16;
+  if (tail)
+    hipLaunchKernelGGL(k_fill_zero_bytes, dim3(1), dim3(kBlock), 0, s,
+                       reinterpret_cast<uint8_t*>(p) + n16 * 16, tail);
+  return hipGetLastError();
+}
+
+template <int K>
+static void init_t(const Geo& g, const PhysParams& ph, void* grid, const uint8_t* flags,
+                   const float* rho0, const float* u0, hipStream_t s) {
+  using S = Storage<K>;
+  hipLaunchKernelGGL(k_init<K>, dim3(g.nblocks), dim3(kBlock), 0, s,
+                     reinterpret_cast<typename S::T*>(grid), flags, rho0, u0, g,
+                     to_phys<typename S::C>(ph));
+}
+
+hipError_t launch_init(int storage, const Geo& g, const PhysParams& ph, void* grid,
+                       const uint8_t* flags, const float* rho0, const float* u0, hipStream_t s) {
+  switch (storage) {
+    case ST_F32: init_t<ST_F32>(g, ph, grid, flags, rho0, u0, s); break;
+    case ST_F16: init_t<ST_F16>(g, ph, grid, flags, rho0, u0, s); break;
+    case ST_BF16: init_t<ST_BF16>(g, ph, grid, flags, rho0, u0, s); break;
+    case ST_F64: init_t<ST_F64>(g, ph, grid, flags, rho0, u0, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int K, bool SOLIDS, bool FORCE>
+static void step_t(const Geo& g, const PhysParams& ph, const void* src, void* dst,
+                   const uint8_t* flags, hipStream_t s) {
+  using S = Storage<K>;
+  hipLaunchKernelGGL((k_step<K, SOLIDS, FORCE>), dim3(g.nblocks), dim3(kBlock), 0, s,
+                     reinterpret_cast<const typename S::T*>(src),
+                     reinterpret_cast<typename S::T*>(dst), flags, g,
+                     to_phys<typename S::C>(ph));
+}
+
+template <int K>
+static void step_k(bool solids, bool force, const Geo& g, const PhysParams& ph, const void* src,
+                   void* dst, const uint8_t* flags, hipStream_t s) {
+  if (solids) {
+    if (force) step_t<K, true, true>(g, ph, src, dst, flags, s);
+    else step_t<K, true, false>(g, ph, src, dst, flags, s);
+  } else {
+    if (force) step_t<K, false, true>(g, ph, src, dst, flags, s);
+    else step_t<K, false, false>(g, ph, src, dst, flags, s);
+  }
+}
+
+hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
+                       const void* src, void* dst, const uint8_t* flags, hipStream_t s) {
+  switch (storage) {
+    case ST_F32: step_k<ST_F32>(solids, force, g, ph, src, dst, flags, s); break;
+    case ST_F16: step_k<ST_F16>(solids, force, g, ph, src, dst, flags, s); break;
+    case ST_BF16: step_k<ST_BF16>(solids, force, g, ph, src, dst, flags, s); break;
+    case ST_F64: step_k<ST_F64>(solids, force, g, ph, src, dst, flags, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int K, typename O>
+static void macro_t(const Geo& g, const PhysParams& ph, const void* grid, const uint8_t* flags,
+                    void* rho, void* u, hipStream_t s) {
+  hipLaunchKernelGGL((k_macro<K, O>), dim3(g.nblocks), dim3(kBlock), 0, s,
+                     reinterpret_cast<const typename Storage<K>::T*>(grid), flags,
+                     reinterpret_cast<O*>(rho), reinterpret_cast<O*>(u), g, O(ph.F[0]),
+                     O(ph.F[1]), O(ph.F[2]), O(1.0 / ph.scale));
+}
+
+template <typename O>
+static hipError_t macro_o(int storage, const Geo& g, const PhysParams& ph, const void* grid,
+                          const uint8_t* flags, void* rho, void* u, hipStream_t s) {
+  switch (storage) {
+    case ST_F32: macro_t<ST_F32, O>(g, ph, grid, flags, rho, u, s); break;
+    case ST_F16: macro_t<ST_F16, O>(g, ph, grid, flags, rho, u, s); break;
+    case ST_BF16: macro_t<ST_BF16, O>(g, ph, grid, flags, rho, u, s); break;
+    case ST_F64: macro_t<ST_F64, O>(g, ph, grid, flags, rho, u, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_macro(int storage, bool out_f64, const Geo& g, const PhysParams& ph,
+                        const void* grid, const uint8_t* flags, void* rho, void* u, hipStream_t s) {
+  return out_f64 ? macro_o<double>(storage, g, ph, grid, flags, rho, u, s)
+                 : macro_o<float>(storage, g, ph, grid, flags, rho, u, s);
+}
+
+template <int K>
+static void reduce_t(const Geo& g, const PhysParams& ph, const void* grid, const uint8_t* flags,
+                     double* scratch, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_partials<K>, dim3(kReduceBlocks), dim3(kBlock), 0, s,
+                     reinterpret_cast<const typename Storage<K>::T*>(grid), flags, g, ph.F[0],
+                     ph.F[1], ph.F[2], 1.0 / ph.scale, scratch);
+}
+
+hipError_t launch_reduce(int storage, const Geo& g, const PhysParams& ph, const void* grid,
+                         const uint8_t* flags, double* scratch, double* out5, hipStream_t s) {
+  switch (storage) {
+    case ST_F32: reduce_t<ST_F32>(g, ph, grid, flags, scratch, s); break;
+    case ST_F16: reduce_t<ST_F16>(g, ph, grid, flags, scratch, s); break;
+    case ST_BF16: reduce_t<ST_BF16>(g, ph, grid, flags, scratch, s); break;
+    case ST_F64: reduce_t<ST_F64>(g, ph, grid, flags, scratch, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_partials<5>, dim3(1), dim3(kBlock), 0, s, scratch, kReduceBlocks, out5);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_seed(const Geo& g, const PhysParams& ph, const float* fT, const uint8_t* flags,
+                           const float* dL_drho, const float* dL_du, float* lam, double* partials,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_seed, dim3(g.nblocks), dim3(kBlock), 0, s, fT, flags, dL_drho, dL_du,
+                     lam, partials, g, float(ph.F[0]), float(ph.F[1]), float(ph.F[2]));
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_step(bool solids, const Geo& g, const PhysParams& ph, const float* fn,
+                           const uint8_t* flags, const float* lam_np1, float* lam_n,
+                           double* partials, hipStream_t s) {
+  if (solids)
+    hipLaunchKernelGGL(k_adj_step<true>, dim3(g.nblocks), dim3(kBlock), 0, s, fn, flags, lam_np1,
+                       lam_n, partials, g, to_phys<float>(ph));
+  else
+    hipLaunchKernelGGL(k_adj_step<false>, dim3(g.nblocks), dim3(kBlock), 0, s, fn, flags, lam_np1,
+                       lam_n, partials, g, to_phys<float>(ph));
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_init(const Geo& g, const uint8_t* flags, const float* lam0, const float* rho0,
+                           const float* u0, float* dL_du0, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_init, dim3(g.nblocks), dim3(kBlock), 0, s, lam0, flags, rho0, u0,
+                     dL_du0, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_finish(const Geo& g, const double* partials, double* out3, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials<3>, dim3(1), dim3(kBlock), 0, s, partials, g.nblocks, out3);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void* c, const void* a, size_t n16, hipStream_t s) {
+  const size_t blocks = (n16 + kBlock * 4 - 1) / (kBlock * 4);
+  hipLaunchKernelGGL(k_copy, dim3(unsigned(blocks)), dim3(kBlock), 0, s,
+                     reinterpret_cast<uint4*>(c), reinterpret_cast<const uint4*>(a), n16);
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -175,3 +175,29 @@ def random_flags(shape, seed, solid_fraction=0.2, noforce_fraction=0.0):
         nf = (rng.random(shape) < noforce_fraction) & (f == 0)
         f |= nf.astype(np.uint8) * FLAG_NOFORCE
     return f
+
+
+def shear_waves(shape, seed, amplitude=0.02):
+    """A cheap smooth velocity [3, nz, ny, nx] (float32) for large boxes: each
+    component is a sum of two single-wavelength sine waves along the two
+    other axes, u_x = A1 sin(2 pi y/ny + p1) + A2 sin(2 pi z/nz + p2) and
+    cyclically, with A ~ U(-1, 1) and p ~ U(0, 2 pi) from SplitMix64(seed) in
+    the order (x: A1 p1 A2 p2, y: ..., z: ...); scaled to max |u_c| <= amplitude."""
+    nz, ny, nx = shape
+    rng = SplitMix64(seed)
+    axes = {0: nx, 1: ny, 2: nz}
+    coords = {0: np.arange(nx, dtype=np.float32)[None, None, :],
+              1: np.arange(ny, dtype=np.float32)[None, :, None],
+              2: np.arange(nz, dtype=np.float32)[:, None, None]}
+    u = np.zeros((3,) + tuple(shape), dtype=np.float32)
+    for c in range(3):
+        others = [a for a in range(3) if a != c]
+        terms = []
+        for a in others:
+            A = 2.0 * rng.uniform() - 1.0
+            p = 2 * math.pi * rng.uniform()
+            terms.append((A, np.sin(np.float32(2 * math.pi / axes[a]) * coords[a] + np.float32(p))))
+        s = abs(terms[0][0]) + abs(terms[1][0])
+        u[c] = (np.float32(amplitude * terms[0][0] / s) * terms[0][1]
+                + np.float32(amplitude * terms[1][0] / s) * terms[1][1])
+    return u

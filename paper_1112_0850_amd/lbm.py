@@ -1,0 +1,208 @@
+"""Python front-end of the gfx950 D3Q19 BGK library.
+
+PyTorch provides device memory and the stream; every step of the solver --
+initialisation, the fused stream-collide update, macroscopic fields, FP64
+reductions, and the adjoint -- runs in the HIP kernels behind the C ABI of
+include/lbm.h.  Shapes are (nz, ny, nx); fields are [nz, ny, nx] and
+[3, nz, ny, nx]; populations [19, nz, ny, x_stride] in the interface order.
+"""
+import ctypes
+
+import torch
+
+from . import _abi as A
+
+STORAGE = {"f32": A.LBM_F32, "f16": A.LBM_F16, "bf16": A.LBM_BF16, "f64": A.LBM_F64}
+TORCH_DTYPE = {A.LBM_F32: torch.float32, A.LBM_F16: torch.float16,
+               A.LBM_BF16: torch.bfloat16, A.LBM_F64: torch.float64}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _aligned(t, what):
+    if t.data_ptr() % 256:
+        raise ValueError(f"{what} must be 256-byte aligned")
+    return t
+
+
+def _as_field(x, shape, dtype, device, what):
+    """A contiguous device tensor of the given shape and dtype (a copy when
+    the caller's tensor differs); None stays None."""
+    if x is None:
+        return None
+    t = torch.as_tensor(x)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+class LBM:
+    """One D3Q19 BGK simulation on a periodic box (walls and obstacles are
+    solid flag bits).  ``storage`` in {'f32', 'f16', 'bf16', 'f64'}."""
+
+    def __init__(self, shape, tau, force=(0.0, 0.0, 0.0), storage="f32", flags=None, u0=None,
+                 rho0=None, f16_scale_log2=0, x_align=0, device="cuda"):
+        self.shape = tuple(int(s) for s in shape)
+        if len(self.shape) != 3:
+            raise ValueError("shape must be (nz, ny, nx)")
+        self.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+        self.dtype = TORCH_DTYPE[self.storage]
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the solver runs on a GPU device")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.tau = float(tau)
+        self.force = tuple(float(f) for f in force)
+        self.params = A.params(self.shape, tau, self.force, self.storage, f16_scale_log2, x_align)
+        xs, gb, sb, ab = A.lbm_query(self.params)
+        self.x_stride, self.grid_bytes, self.adj_partials_bytes = xs, gb, ab
+        nz, ny, nx = self.shape
+        self.flags = _as_field(flags, self.shape, torch.uint8, self.device, "flags")
+        self.rho0 = _as_field(rho0, self.shape, torch.float32, self.device, "rho0")
+        self.u0 = _as_field(u0, (3,) + self.shape, torch.float32, self.device, "u0")
+        self.grids = [_aligned(torch.empty(gb, dtype=torch.uint8, device=self.device), "grid")
+                      for _ in range(2)]
+        self.scratch = _aligned(torch.empty(sb, dtype=torch.uint8, device=self.device), "scratch")
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = A.lbm_init(self.params, _ptr(self.grids[0]), _ptr(self.grids[1]),
+                              _ptr(self.flags), _ptr(self.scratch), _ptr(self.rho0),
+                              _ptr(self.u0), ctypes.c_void_p(self.stream.cuda_stream))
+
+    # -- state --------------------------------------------------------------
+    @property
+    def t(self):
+        return A.lbm_time(self.ctx)
+
+    @property
+    def current(self):
+        return A.lbm_current(self.ctx)
+
+    def grid_view(self, raw):
+        """A raw grid buffer viewed as [19, nz, ny, x_stride] of the storage dtype."""
+        nz, ny, _ = self.shape
+        n = 19 * nz * ny * self.x_stride
+        return raw.view(self.dtype)[:n].view(19, nz, ny, self.x_stride)
+
+    def populations(self):
+        """View of the current grid: offsets g = f* - w (FP16: 2^s g)."""
+        return self.grid_view(self.grids[self.current])
+
+    def new_grid(self):
+        return _aligned(torch.empty(self.grid_bytes, dtype=torch.uint8, device=self.device), "grid")
+
+    # -- the hot path -------------------------------------------------------
+    def step(self, n=1):
+        A.lbm_step(self.ctx, n)
+        return self
+
+    def step_from(self, src, dst):
+        A.lbm_step_from(self.ctx, _ptr(_aligned(src, "src")), _ptr(_aligned(dst, "dst")))
+
+    def macroscopics(self, f64=False):
+        dt = torch.float64 if f64 else torch.float32
+        rho = torch.empty(self.shape, dtype=dt, device=self.device)
+        u = torch.empty((3,) + self.shape, dtype=dt, device=self.device)
+        (A.lbm_macroscopics_f64 if f64 else A.lbm_macroscopics)(self.ctx, _ptr(rho), _ptr(u))
+        return rho, u
+
+    def reduce(self):
+        """Device tensor (float64, 5): mass, momentum x/y/z, kinetic energy."""
+        out = torch.empty(5, dtype=torch.float64, device=self.device)
+        A.lbm_reduce(self.ctx, _ptr(out))
+        return out
+
+    # -- checkpoint / resume --------------------------------------------------
+    def save(self, dst=None):
+        dst = self.new_grid() if dst is None else _aligned(dst, "dst")
+        A.lbm_save(self.ctx, _ptr(dst))
+        return dst
+
+    def restore(self, src, t):
+        A.lbm_restore(self.ctx, _ptr(src), t)
+
+    def set_current(self, parity, t):
+        A.lbm_set_current(self.ctx, parity, t)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            A.lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def stream_copy(dst, src, stream=None):
+    """STREAM copy dst = src of whole tensors on the GPU (bandwidth probe)."""
+    if dst.numel() * dst.element_size() != src.numel() * src.element_size():
+        raise ValueError("size mismatch")
+    s = torch.cuda.current_stream() if stream is None else stream
+    A.lbm_stream_copy(_ptr(_aligned(dst, "dst")), _ptr(_aligned(src, "src")),
+                      src.numel() * src.element_size(), ctypes.c_void_p(s.cuda_stream))
+
+
+class _Rollout(torch.autograd.Function):
+    """(rho_T, u_T) after `steps` updates from f*(0) = f^eq(1, u0) under the
+    body force g; backward runs the hand-written adjoint kernels with forward
+    checkpoints every k steps and recomputation inside each segment."""
+
+    @staticmethod
+    def forward(ctx, u0, g, steps, tau, flags, k):
+        force = [float(v) for v in g.detach().double().cpu().tolist()]
+        sim = LBM(u0.shape[1:], tau, force, "f32", flags=flags, u0=u0.detach(), device=u0.device)
+        ckpts = []
+        for t in range(steps):
+            if t % k == 0:
+                ckpts.append(sim.save())
+            sim.step(1)
+        rho, u = sim.macroscopics()
+        ctx.sim, ctx.ckpts, ctx.steps, ctx.k = sim, ckpts, steps, k
+        ctx.g_meta = (g.dtype, g.device)
+        return rho, u
+
+    @staticmethod
+    def backward(ctx, g_rho, g_u):
+        sim, ckpts, steps, k = ctx.sim, ctx.ckpts, ctx.steps, ctx.k
+        dev = sim.device
+        nfl = sim.grid_bytes // 4
+        lam = [torch.zeros(nfl, dtype=torch.float32, device=dev) for _ in range(2)]
+        partials = torch.zeros(sim.adj_partials_bytes // 8, dtype=torch.float64, device=dev)
+        gr = None if g_rho is None else g_rho.to(torch.float32).contiguous()
+        gu = None if g_u is None else g_u.to(torch.float32).contiguous()
+        A.lbm_adjoint_seed(sim.ctx, _ptr(gr), _ptr(gu), _ptr(lam[0]), _ptr(partials))
+        cur = 0
+        seg = [None] + [sim.new_grid() for _ in range(min(k, steps) - 1)]
+        for s in range(len(ckpts) - 1, -1, -1):
+            t0, t1 = s * k, min(s * k + k, steps)
+            seg[0] = ckpts[s]
+            for j in range(1, t1 - t0):
+                sim.step_from(seg[j - 1], seg[j])
+            for n in range(t1 - 1, t0 - 1, -1):
+                A.lbm_adjoint_step(sim.ctx, _ptr(seg[n - t0]), _ptr(lam[cur]), _ptr(lam[cur ^ 1]),
+                                   _ptr(partials))
+                cur ^= 1
+        du0 = torch.empty((3,) + sim.shape, dtype=torch.float32, device=dev)
+        A.lbm_adjoint_init(sim.ctx, _ptr(lam[cur]), _ptr(sim.rho0), _ptr(sim.u0), _ptr(du0))
+        dF = torch.empty(3, dtype=torch.float64, device=dev)
+        A.lbm_adjoint_finish_dF(sim.ctx, _ptr(partials), _ptr(dF))
+        gdt, gdev = ctx.g_meta
+        return du0, dF.to(device=gdev, dtype=gdt), None, None, None, None
+
+
+def rollout(u0, g, *, steps, tau, flags=None, checkpoint_every=20):
+    """Differentiable D3Q19 BGK rollout (FP32 storage): returns (rho_T, u_T)
+    with gradients for the initial velocity ``u0`` [3, nz, ny, nx] and the
+    body-force density ``g`` [3]."""
+    if u0.dim() != 4 or u0.shape[0] != 3:
+        raise ValueError("u0 must be [3, nz, ny, nx]")
+    if g.numel() != 3:
+        raise ValueError("g must have 3 components")
+    if steps < 1 or checkpoint_every < 1:
+        raise ValueError("steps and checkpoint_every must be >= 1")
+    return _Rollout.apply(u0, g.reshape(3), int(steps), float(tau), flags, int(checkpoint_every))

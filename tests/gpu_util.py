@@ -1,0 +1,48 @@
+"""Helpers shared by the GPU tests: moving states between the library's
+grid layout and the oracle's layout, and the error measures used in the
+parity bars.  Test-side plumbing only (layout and dtype conversion)."""
+import numpy as np
+import torch
+
+from tests import lattice_ref as R
+
+W = R.e_w_opp()[1]
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+def grid_to_f(sim, grid=None, offsets=False):
+    """The populations of a grid (default: current) as float64 [19, nz, ny, nx];
+    f = g / scale + w unless offsets=True.  Solid cells come back as stored."""
+    g = sim.populations() if grid is None else sim.grid_view(grid)
+    nz, ny, nx = sim.shape
+    a = g[..., :nx].to(torch.float64).cpu().numpy()
+    if sim.storage == 1:  # FP16 holds 2^s g
+        a = a / 2.0 ** sim.params.f16_scale_log2
+    if not offsets:
+        a = a + W[:, None, None, None]
+    return a
+
+
+def f_to_grid(sim, f, offsets=False, flags=None):
+    """Write float64 [19, nz, ny, nx] populations (or offsets) into the current
+    grid, rounding to the storage type; solid cells get 0."""
+    g = np.array(f, dtype=np.float64)
+    if not offsets:
+        g = g - W[:, None, None, None]
+    if flags is not None:
+        g[:, (flags & 1) == 1] = 0.0
+    if sim.storage == 1:
+        g = g * 2.0 ** sim.params.f16_scale_log2
+    nz, ny, nx = sim.shape
+    view = sim.populations()
+    view[..., :nx].copy_(torch.from_numpy(g).to(view.dtype))
+    torch.cuda.synchronize()
+
+
+def rel_linf(a, b, mask=None):
+    if mask is not None:
+        a, b = a[..., mask], b[..., mask]
+    return float(np.abs(a - b).max() / np.abs(b).max())

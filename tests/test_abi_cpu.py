@@ -1,0 +1,131 @@
+"""Host-side checks of the C ABI (no GPU): the library loads and exports
+every symbol include/lbm.h declares, its tables match the interface order,
+its byte model matches the paper's (Sec. 4), sizes are as documented, and
+invalid arguments are rejected on the host with a message."""
+import ctypes
+import json
+import math
+import os
+import re
+
+import pytest
+
+from paper_1112_0850_amd import _abi as A
+from tests import lattice_ref as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_A-Z]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = A.lib()
+    names = _declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(A._SIGNATURES), "binding and header disagree"
+
+
+def test_lattice_tables_match_interface_order():
+    e, w, opp = A.lbm_lattice()
+    e_r, w_r, opp_r = R.e_w_opp()
+    assert [tuple(map(int, c)) for c in e_r] == e
+    assert list(w_r) == w
+    assert list(opp_r) == opp
+
+
+def test_byte_model_matches_paper():
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "byte_model.json")))
+    assert A.lbm_bytes_per_update(A.LBM_F32) == gold["bytes_per_update_gpu"]["sp"]
+    assert A.lbm_bytes_per_update(A.LBM_F64) == gold["bytes_per_update_gpu"]["dp"]
+    assert A.lbm_bytes_per_update(A.LBM_F16) == 76
+    assert A.lbm_bytes_per_update(A.LBM_BF16) == 76
+    assert A.lbm_bytes_per_update(7) == 0
+    # the CPU variant adds the write-allocate transfer: 3 transfers per PDF
+    assert 19 * 3 * 4 == gold["bytes_per_update_cpu_write_allocate"]["sp"]
+    assert 19 * 3 * 8 == gold["bytes_per_update_cpu_write_allocate"]["dp"]
+    # Table 4: the model is STREAM bandwidth / bytes per update
+    node = gold["table4_mflups"]["Intel X5650 node"]
+    assert round(node["stream_gbs"] * 1e3 / 228) == node["sp"]
+    assert round(node["stream_gbs"] * 1e3 / 456) == node["dp"]
+    for row in ("C2070", "C2070 ECC", "C1060"):
+        r = gold["table4_mflups"][row]
+        assert abs(r["sp"] * 152 - r["dp"] * 304) <= 304  # one bandwidth behind both columns
+
+
+@pytest.mark.parametrize("shape,storage,align,xs", [
+    ((4, 5, 1), A.LBM_F32, 0, 64), ((3, 2, 65), A.LBM_F32, 0, 128), ((3, 2, 65), A.LBM_F64, 1, 65),
+    ((512, 512, 512), A.LBM_F16, 0, 512), ((2, 2, 100), A.LBM_BF16, 16, 112)])
+def test_query_sizes(shape, storage, align, xs):
+    p = A.params(shape, 0.6, storage=storage, x_align=align)
+    x_stride, gb, sb, ab = A.lbm_query(p)
+    es = {A.LBM_F32: 4, A.LBM_F64: 8, A.LBM_F16: 2, A.LBM_BF16: 2}[storage]
+    nz, ny, nx = shape
+    assert x_stride == xs
+    assert gb >= 19 * nz * ny * xs * es and gb % 256 == 0 and gb - 19 * nz * ny * xs * es < 256
+    assert sb == 1024 * 5 * 8
+    nblocks = -(-(-(-nx // 64) * ny * nz) // 4)
+    assert ab == nblocks * 3 * 8
+
+
+def test_query_limits():
+    A.lbm_query(A.params((768, 768, 768), 0.55, storage=A.LBM_F32))
+    A.lbm_query(A.params((640, 640, 640), 0.55, storage=A.LBM_F64))
+    with pytest.raises(A.LBMError) as e:
+        A.lbm_query(A.params((1024, 1024, 1024), 0.55, storage=A.LBM_F32))
+    assert e.value.status == A.LBM_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(shape=(0, 4, 4), tau=0.6), "dimensions"),
+    (dict(shape=(4, 4, 4), tau=0.5), "tau"),
+    (dict(shape=(4, 4, 4), tau=float("nan")), "tau"),
+    (dict(shape=(4, 4, 4), tau=-math.inf), "tau"),
+    (dict(shape=(4, 4, 4), tau=0.6, force=(math.inf, 0, 0)), "force"),
+    (dict(shape=(4, 4, 4), tau=0.6, storage=9), "storage"),
+    (dict(shape=(4, 4, 4), tau=0.6, storage=A.LBM_F16, f16_scale_log2=30), "scale"),
+    (dict(shape=(4, 4, 4), tau=0.6, x_align=-2), "x_align"),
+])
+def test_invalid_params_rejected(kw, msg):
+    with pytest.raises(A.LBMError) as e:
+        A.lbm_query(A.params(**kw))
+    assert e.value.status == A.LBM_E_ARG
+    assert msg in str(e.value)
+
+
+def test_infinite_tau_accepted():
+    A.lbm_query(A.params((4, 4, 4), math.inf))
+
+
+def test_init_argument_errors_before_any_gpu_work():
+    p = A.params((4, 4, 4), 0.6)
+    fake = ctypes.c_void_p(0x10000)
+    with pytest.raises(A.LBMError) as e:
+        A.lbm_init(p, None, fake, None, fake, None, None, None)
+    assert e.value.status == A.LBM_E_ARG and "grid" in str(e.value)
+    with pytest.raises(A.LBMError) as e:
+        A.lbm_init(p, fake, fake, None, fake, None, None, None)
+    assert "differ" in str(e.value)
+    with pytest.raises(A.LBMError) as e:
+        A.lbm_init(p, ctypes.c_void_p(0x10010), fake, None, fake, None, None, None)
+    assert "aligned" in str(e.value)
+    with pytest.raises(A.LBMError) as e:
+        A.lbm_init(p, fake, ctypes.c_void_p(0x20000), None, None, None, None, None)
+    assert "scratch" in str(e.value)
+    assert A.lbm_last_error() != ""
+
+
+def test_null_context_rejected():
+    with pytest.raises(A.LBMError) as e:
+        A.lbm_step(None, 1)
+    assert e.value.status == A.LBM_E_ARG
+    with pytest.raises(A.LBMError):
+        A.lbm_reduce(None, None)
+    assert A.lbm_current(None) == -1 and A.lbm_time(None) == -1
+    with pytest.raises(A.LBMError):
+        A.lbm_stream_copy(ctypes.c_void_p(0x100), ctypes.c_void_p(0x200), 17, None)

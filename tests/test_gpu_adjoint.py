@@ -1,0 +1,176 @@
+"""GPU parity of the discrete adjoint: each adjoint kernel against the FP64
+oracle's adjoint, the full checkpointed rollout gradient against the
+oracle's reverse sweep and against FP64 central finite differences of the
+oracle's forward map, and bit-identical gradients for any checkpoint spacing."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1112_0850_amd import _abi as A
+from paper_1112_0850_amd import inputs as I
+from paper_1112_0850_amd.lbm import LBM, rollout
+from tests.gpu_util import f_to_grid, grid_to_f, rel_linf, say
+from tests.test_oracle_adjoint import rollout_grad, rollout_loss
+
+pytestmark = pytest.mark.gpu
+P = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def _to_lam_grid(sim, lam):
+    """float64 [19, nz, ny, nx] -> zero-padded FP32 buffer in the grid layout."""
+    nz, ny, nx = sim.shape
+    buf = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
+    v = buf[:19 * nz * ny * sim.x_stride].view(19, nz, ny, sim.x_stride)
+    v[..., :nx].copy_(torch.from_numpy(lam).float())
+    return buf
+
+
+def _from_lam_grid(sim, buf):
+    nz, ny, nx = sim.shape
+    v = buf[:19 * nz * ny * sim.x_stride].view(19, nz, ny, sim.x_stride)
+    return v[..., :nx].double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def case():
+    shape = (9, 10, 70)
+    flags = I.random_flags(shape, 77, solid_fraction=0.2, noforce_fraction=0.15)
+    rng = np.random.default_rng(4)
+    u0 = 0.03 * (rng.random((3,) + shape) - 0.5)
+    u0[:, flags & 1 == 1] = 0
+    tau, F = 0.62, (3e-4, -2e-4, 1e-4)
+    fn = O.step(O.init(shape, flags, None, _f32(u0)), tau, F, flags, n=3)
+    lam1 = rng.standard_normal((19,) + shape)
+    lam1[:, flags & 1 == 1] = 0
+    return dict(shape=shape, flags=flags, tau=tau, F=F, fn=fn, lam1=_f32(lam1), u0=_f32(u0))
+
+
+def _sim(c):
+    return LBM(c["shape"], c["tau"], c["F"], "f32", flags=c["flags"])
+
+
+def test_adjoint_step_kernel_vs_oracle(case):
+    say("adjoint step kernel vs oracle", case["shape"])
+    sim = _sim(case)
+    f_to_grid(sim, case["fn"], flags=case["flags"])
+    fn32 = grid_to_f(sim)  # the FP32-rounded state the kernel sees
+    lam1 = _to_lam_grid(sim, case["lam1"])
+    lam0 = torch.zeros_like(lam1)
+    part = torch.zeros(sim.adj_partials_bytes // 8, dtype=torch.float64, device="cuda")
+    A.lbm_adjoint_step(sim.ctx, P(sim.grids[sim.current]), P(lam1), P(lam0), P(part))
+    dF = torch.empty(3, dtype=torch.float64, device="cuda")
+    A.lbm_adjoint_finish_dF(sim.ctx, P(part), P(dF))
+    torch.cuda.synchronize()
+    ref, dF_ref = O.adjoint_step(fn32, case["lam1"], case["tau"], case["F"], case["flags"])
+    got = _from_lam_grid(sim, lam0)
+    e = rel_linf(got, ref)
+    eF = np.abs(dF.cpu().numpy() - dF_ref).max() / np.abs(dF_ref).max()
+    say(f"  lambda rel L-inf {e:.2e}, dL/dF rel {eF:.2e}")
+    assert e <= 1e-5 and eF <= 1e-5
+    assert not got[:, case["flags"] & 1 == 1].any()
+
+
+def test_adjoint_seed_and_init_kernels_vs_oracle(case):
+    say("adjoint seed/init kernels vs oracle")
+    sim = _sim(case)
+    f_to_grid(sim, case["fn"], flags=case["flags"])
+    fT = grid_to_f(sim)
+    rng = np.random.default_rng(8)
+    shape = case["shape"]
+    gr, gu = _f32(rng.standard_normal(shape)), _f32(rng.standard_normal((3,) + shape))
+    lam = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
+    part = torch.zeros(sim.adj_partials_bytes // 8, dtype=torch.float64, device="cuda")
+    grt, gut = torch.from_numpy(gr).float().cuda(), torch.from_numpy(gu).float().cuda()
+    A.lbm_adjoint_seed(sim.ctx, P(grt), P(gut), P(lam), P(part))
+    dF = torch.empty(3, dtype=torch.float64, device="cuda")
+    A.lbm_adjoint_finish_dF(sim.ctx, P(part), P(dF))
+    lam_ref, dF_ref = O.adjoint_seed(fT, gr, gu, case["F"], case["flags"])
+    torch.cuda.synchronize()
+    assert rel_linf(_from_lam_grid(sim, lam), lam_ref) <= 1e-6
+    assert np.abs(dF.cpu().numpy() - dF_ref).max() <= 1e-6 * np.abs(dF_ref).max()
+    # init: dL/du0 from lambda^0 at (rho0 = 1, u0)
+    lam0 = _to_lam_grid(sim, case["lam1"])
+    u0t = torch.from_numpy(case["u0"]).float().cuda()
+    du0 = torch.empty((3,) + shape, dtype=torch.float32, device="cuda")
+    A.lbm_adjoint_init(sim.ctx, P(lam0), None, P(u0t), P(du0))
+    ref, _ = O.adjoint_init(case["lam1"], case["u0"], case["flags"])
+    torch.cuda.synchronize()
+    assert rel_linf(du0.double().cpu().numpy(), ref) <= 1e-6
+
+
+def _gpu_grad(u0, target, F, flags, tau, steps, k):
+    u0t = torch.from_numpy(u0).float().cuda().requires_grad_(True)
+    g = torch.tensor(F, dtype=torch.float64, requires_grad=True)
+    rho, u = rollout(u0t, g, steps=steps, tau=tau, flags=flags, checkpoint_every=k)
+    fl = torch.ones(u0.shape[1:], dtype=torch.bool, device="cuda") if flags is None else \
+        torch.from_numpy((flags & 1) == 0).cuda()
+    tt = torch.from_numpy(target).float().cuda()
+    loss = ((u - tt) ** 2)[:, fl].mean()
+    loss.backward()
+    return u0t.grad.double().cpu().numpy(), g.grad.cpu().numpy(), float(loss)
+
+
+def test_rollout_gradient_vs_oracle_adjoint():
+    """16^3 with solids and no-force cells, 30 steps, k = 7."""
+    n, tau, steps = 16, 0.6, 30
+    shape = (n, n, n)
+    say("rollout gradient vs oracle adjoint", shape)
+    flags = I.random_flags(shape, 13, solid_fraction=0.1, noforce_fraction=0.1)
+    u0 = _f32(I.smooth_field(n, 2024, amplitude=0.02, modes=4))
+    u0[:, flags & 1 == 1] = 0
+    target = _f32(I.smooth_field(n, 7, amplitude=0.02, modes=4))
+    F = np.array([1e-4, -5e-5, 2e-5])
+    du0, dF, _ = _gpu_grad(u0, target, F, flags, tau, steps, 7)
+    du0_ref, dF_ref = rollout_grad(u0, F, flags, tau, steps, target)
+    e_u, e_F = rel_linf(du0, du0_ref), np.abs(dF - dF_ref).max() / np.abs(dF_ref).max()
+    say(f"  dL/du0 rel L-inf {e_u:.2e}, dL/dg rel {e_F:.2e}")
+    assert e_u <= 1e-4 and e_F <= 1e-4
+
+
+def test_rollout_gradient_vs_central_differences():
+    """Periodic 32^3, smooth u0 (amplitude 0.02), g = (1e-6, 0, 0), tau = 0.6,
+    200 steps, k = 20: directional derivatives along 4 smooth directions and
+    each force component against FP64 central differences of the oracle
+    (eps = 1e-4 on u0, 1e-6 on g); bar 1e-4 relative."""
+    n, tau, steps = 32, 0.6, 200
+    say("rollout gradient vs central differences, 32^3", steps, "steps")
+    u0 = _f32(I.smooth_field(n, 2024, amplitude=0.02))
+    target = _f32(I.smooth_field(n, 7, amplitude=0.02))
+    F = np.array([1e-6, 0.0, 0.0])
+    du0, dF, _ = _gpu_grad(u0, target, F, None, tau, steps, 20)
+    for s in (101, 102, 103, 104):
+        v = I.smooth_field(n, s, amplitude=1.0)
+        eps = 1e-4
+        fd = (rollout_loss(u0 + eps * v, F, None, tau, steps, target)
+              - rollout_loss(u0 - eps * v, F, None, tau, steps, target)) / (2 * eps)
+        ad = float((du0 * v).sum())
+        say(f"  direction {s}: adjoint {ad:.6e}  FD {fd:.6e}  rel {abs(ad - fd) / abs(fd):.2e}")
+        assert abs(ad - fd) <= 1e-4 * abs(fd)
+    for a in range(3):
+        d = np.zeros(3)
+        d[a] = 1e-6
+        fd = (rollout_loss(u0, F + d, None, tau, steps, target)
+              - rollout_loss(u0, F - d, None, tau, steps, target)) / 2e-6
+        say(f"  g[{a}]: adjoint {dF[a]:.6e}  FD {fd:.6e}")
+        assert abs(dF[a] - fd) <= 1e-4 * abs(fd)
+
+
+def test_checkpoint_spacing_gives_identical_gradients():
+    n, tau, steps = 32, 0.6, 40
+    say("checkpoint spacing 1 / 7 / 20 / 40")
+    flags = I.random_flags((n, n, n), 3, solid_fraction=0.05)
+    u0 = _f32(I.smooth_field(n, 5, amplitude=0.02, modes=4))
+    u0[:, flags & 1 == 1] = 0
+    target = _f32(I.smooth_field(n, 6, amplitude=0.02, modes=4))
+    F = np.array([1e-5, 0, 0])
+    ref = _gpu_grad(u0, target, F, flags, tau, steps, 1)
+    for k in (7, 20, 40):
+        got = _gpu_grad(u0, target, F, flags, tau, steps, k)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), k

@@ -1,0 +1,118 @@
+"""Parity at the benchmark's full size and launch configuration: the 512^3
+porous box (10% spheres, seed 12345, tau = 0.55, g_x = 1e-6), one fused step
+checked cell by cell on sampled cells, where the oracle recomputes each
+sampled cell from its 3^3 neighbourhood of the previous state; and the
+adjoint kernel at the rollout's 128^3 size, checked on 5^3 neighbourhoods."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1112_0850_amd import _abi as A
+from paper_1112_0850_amd import inputs as I
+from paper_1112_0850_amd.lbm import LBM
+from tests.gpu_util import W, say
+
+pytestmark = pytest.mark.gpu
+N = 512
+TAU, F = 0.55, (1e-6, 0.0, 0.0)
+
+
+@pytest.fixture(scope="module")
+def geometry():
+    flags = I.sphere_pack((N, N, N), 0.10, seed=12345)
+    u0 = I.shear_waves((N, N, N), seed=21, amplitude=0.02)
+    u0[:, flags & 1 == 1] = 0
+    return flags, torch.from_numpy(u0)
+
+
+def _crop(view, z, y, x, r, nz, ny, nx):
+    """[19, 2r+1, 2r+1, 2r+1] periodic crop of a [19, nz, ny, xs] device view."""
+    zi = torch.tensor([(z + d) % nz for d in range(-r, r + 1)], device=view.device)
+    yi = torch.tensor([(y + d) % ny for d in range(-r, r + 1)], device=view.device)
+    xi = torch.tensor([(x + d) % nx for d in range(-r, r + 1)], device=view.device)
+    return view[:, zi[:, None, None], yi[None, :, None], xi[None, None, :]]
+
+
+def _fcrop(flags, z, y, x, r):
+    n = flags.shape
+    zi = [(z + d) % n[0] for d in range(-r, r + 1)]
+    yi = [(y + d) % n[1] for d in range(-r, r + 1)]
+    xi = [(x + d) % n[2] for d in range(-r, r + 1)]
+    return np.ascontiguousarray(flags[np.ix_(zi, yi, xi)])
+
+
+@pytest.mark.parametrize("storage,s", [("f32", 0), ("f16", 12), ("bf16", 0)])
+def test_sampled_step_at_full_size(geometry, storage, s):
+    flags, u0 = geometry
+    say(f"full size {N}^3 porous, {storage}: sampled one-step parity")
+    sim = LBM((N, N, N), TAU, F, storage, flags=flags, u0=u0, f16_scale_log2=s)
+    sim.step(3)
+    prev = sim.save()
+    sim.step(1)
+    torch.cuda.synchronize()
+    pv, cv = sim.grid_view(prev), sim.populations()
+    scale = 2.0 ** s
+    rng = np.random.default_rng(2024)
+    fluid = np.flatnonzero((flags & 1 == 0).ravel())
+    cells = rng.choice(fluid, size=256, replace=False)
+    worst = 0.0
+    gmax = 0.0
+    for c in cells:
+        z, rem = divmod(int(c), N * N)
+        y, x = divmod(rem, N)
+        g = _crop(pv, z, y, x, 1, N, N, N).double().cpu().numpy() / scale
+        fl = _fcrop(flags, z, y, x, 1)
+        f = g + W[:, None, None, None]
+        f[:, fl & 1 == 1] = 0
+        ref = O.step(f, TAU, F, fl, n=1)[:, 1, 1, 1] - W
+        got = cv[:, z, y, x].double().cpu().numpy() / scale
+        if storage == "f32":
+            err = np.abs(got - ref)
+            bound = 1e-6 * np.abs(ref).max() + 1e-12
+        else:
+            dt = np.float16 if storage == "f16" else None
+            if dt is not None:
+                ulp = np.spacing(np.abs(ref * scale).astype(np.float16)).astype(np.float64) / scale
+            else:  # bfloat16: 8 significant bits
+                ulp = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(ref), 1e-38))) - 7)
+            err = np.abs(got - ref) - 0.5 * ulp
+            bound = 2e-6 * np.abs(ref).max()
+        worst = max(worst, float(err.max()))
+        gmax = max(gmax, float(np.abs(ref).max()))
+        assert (err <= bound).all(), (storage, z, y, x, err.max(), bound)
+    say(f"  worst excess error {worst:.2e} (offset scale {gmax:.2e})")
+    del sim, prev
+    torch.cuda.empty_cache()
+
+
+def test_sampled_adjoint_step_at_rollout_size():
+    n = 128
+    say(f"adjoint kernel at {n}^3: sampled parity on 5^3 neighbourhoods")
+    u0 = torch.from_numpy(I.smooth_field(n, 2024, amplitude=0.02))
+    sim = LBM((n, n, n), 0.6, (1e-6, 0, 0), "f32", u0=u0)
+    sim.step(5)
+    rng = np.random.default_rng(6)
+    lam1 = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
+    v1 = lam1[:19 * n * n * sim.x_stride].view(19, n, n, sim.x_stride)
+    v1[..., :n].copy_(torch.from_numpy(rng.standard_normal((19, n, n, n)).astype(np.float32)))
+    lam0 = torch.zeros_like(lam1)
+    part = torch.zeros(sim.adj_partials_bytes // 8, dtype=torch.float64, device="cuda")
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    A.lbm_adjoint_step(sim.ctx, P(sim.grids[sim.current]), P(lam1), P(lam0), P(part))
+    torch.cuda.synchronize()
+    v0 = lam0[:19 * n * n * sim.x_stride].view(19, n, n, sim.x_stride)
+    fv = sim.populations()
+    worst = 0.0
+    for _ in range(64):
+        z, y, x = (int(v) for v in rng.integers(0, n, size=3))
+        f = _crop(fv, z, y, x, 2, n, n, n).double().cpu().numpy() + W[:, None, None, None]
+        l1 = _crop(v1, z, y, x, 2, n, n, n).double().cpu().numpy()
+        ref, _ = O.adjoint_step(f, l1, 0.6, (1e-6, 0, 0), None)
+        got = v0[:, z, y, x].double().cpu().numpy()
+        e = np.abs(got - ref[:, 2, 2, 2]).max() / np.abs(ref[:, 2, 2, 2]).max()
+        worst = max(worst, e)
+        assert e <= 1e-5, (z, y, x, e)
+    say(f"  worst relative error {worst:.2e}")
