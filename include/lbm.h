@@ -21,16 +21,25 @@
  *  - Population grid ("grid"): structure of arrays [19][nz][ny][x_stride],
  *    x contiguous, x_stride >= nx from lbm_query (padding cells after each
  *    x-row, never computed -- the paper's Sec. 6 alignment padding).  Each
- *    element holds the OFFSET g_i = f_i - w_i of the post-collision
- *    population f*_i after the latest step, in the storage type:
+ *    element of a fluid cell holds the OFFSET g_i = f_i - w_i of the
+ *    post-collision population f*_i after the latest step, in the storage
+ *    type:
  *      LBM_F32  float,  LBM_F64 double,  LBM_BF16 bfloat16 (g),
  *      LBM_F16  IEEE binary16 holding 2^s * g, s = f16_scale_log2.
  *    Every store rounds to nearest-even.  Collision arithmetic is FP32 for
  *    F32/F16/BF16 storage and FP64 for F64 storage.
+ *    Solid cells carry no state of their own; their slots serve as ghost
+ *    slots of the bounce-back: slot i of a solid cell s holds a copy of
+ *    g_opp(i) of the fluid cell s + c_i (when that cell is fluid), so that
+ *    the pull of that cell reads its bounced value at the plain shifted
+ *    address.  Every other solid slot and all padding stay 0.  The library
+ *    maintains the ghost slots itself (init, step, save/restore); after
+ *    writing a grid from outside, call lbm_refresh_ghosts.
  *  - Scalar fields are [nz][ny][nx], vector fields [3][nz][ny][nx] (no
  *    padding).  flags are uint8 [nz][ny][nx]: bit0 LBM_FLAG_SOLID (obstacle
  *    cell, never read or written), bit1 LBM_FLAG_NOFORCE (fluid cell without
- *    body force); other bits must be 0.  flags == NULL means all fluid.
+ *    body force); other bits are reserved and ignored.  flags == NULL means
+ *    all fluid.
  *  - All axes are periodic; walls are rows of solid cells.
  *  - Time levels: after lbm_init the current grid holds f*(0) = f^eq(rho0,u0)
  *    (solid cells 0); each step streams with half-way bounce-back and then
@@ -153,6 +162,11 @@ int32_t lbm_current(const lbm_ctx* ctx);
 int64_t lbm_time(const lbm_ctx* ctx);
 lbm_status lbm_set_current(lbm_ctx* ctx, int32_t parity, int64_t t);
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
+
+/* Rewrites the ghost slots of the current grid from its fluid cells (needed
+ * only after the caller has written populations into a grid directly).
+ * No-op without flags.  Errors: LBM_E_ARG, LBM_E_HIP. */
+lbm_status lbm_refresh_ghosts(lbm_ctx* ctx);
 
 /* Device-to-device copy of the current grid to `dst` (lbm_save), or of `src`
  * into the current grid with time t (lbm_restore); grid_bytes each, enqueued

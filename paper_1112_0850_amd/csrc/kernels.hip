@@ -131,29 +131,6 @@ __device__ __forceinline__ C cdot(int i, C x, C y, C z) {
   return r;
 }
 
-// Pull streaming with half-way bounce-back: f_i(x) = f*_i(x - c_i) when that
-// cell is fluid, else f*_{opp i}(x).
-template <int K, bool SOLIDS>
-__device__ __forceinline__ void pull(const typename Storage<K>::T* __restrict__ src,
-                                     const uint8_t* __restrict__ flags, const Geo& g,
-                                     const Nbhd& n, typename Storage<K>::C inv_scale,
-                                     typename Storage<K>::C* f) {
-  using T = typename Storage<K>::T;
-  bool bb[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i)
-    bb[i] = SOLIDS && i != 0 && (flags[src_foff(n, i)] & FLAG_SOLID);
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const T* p = src + size_t(i) * g.plane + src_off(n, i);
-    if (SOLIDS && i != 0) {
-      const T* q = src + size_t(D3Q19::opp[i]) * g.plane + n.own;
-      p = bb[i] ? q : p;
-    }
-    f[i] = Storage<K>::load(*p, inv_scale);
-  }
-}
-
 // Moments of an offset population set: delta_rho and j.
 template <typename C>
 __device__ __forceinline__ void moments(const C* f, C& drho, C& jx, C& jy, C& jz) {
@@ -220,28 +197,71 @@ __device__ __forceinline__ void collide(C* f, C omega, C Fx, C Fy, C Fz) {
 
 // ---------------------------------------------------------------------------
 // Fused stream-collide step.
+//
+// Half-way bounce-back through ghost slots: a fluid cell x whose link i
+// points into a solid cell s = x + c_i stores f*_i(x) both in its own slot i
+// and in slot opp(i) of s.  The next step's pull of x in direction opp(i)
+// reads the source x - c_opp(i) = s, slot opp(i), which is f*_i(x) -- the
+// half-way bounce-back value f_opp(i)(x) = f*_i(x).  Every pull therefore
+// loads x - c_i unconditionally, with no flag test between the flag loads and
+// the population loads; the flags are consumed only by the stores.  Each
+// ghost slot has exactly one writer (s - c_i), so steps stay race-free.  The
+// pulls of solid cells are issued speculatively (their lanes stop after the
+// loads) so that no load waits for the cell's own flag.
 // ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void stream_store(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 template <int K, bool SOLIDS, bool FORCE>
 __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* __restrict__ src,
                                                  typename Storage<K>::T* __restrict__ dst,
                                                  const uint8_t* __restrict__ flags, Geo g,
                                                  Phys<typename Storage<K>::C> ph) {
   using C = typename Storage<K>::C;
+  using T = typename Storage<K>::T;
   const Loc l = locate(g);
   if (!l.valid) return;
   const Nbhd n = neighbourhood(g, l);
   uint8_t own = 0;
+  bool into_solid[Q];  // link i points into a solid cell x + c_i (the pull source of opp(i))
   if (SOLIDS) {
     own = flags[n.fown];
-    if (own & FLAG_SOLID) return;  // obstacle cells are never read or written
+#pragma unroll
+    for (int i = 1; i < Q; ++i) into_solid[i] = flags[src_foff(n, D3Q19::opp[i])] & FLAG_SOLID;
   }
   C f[Q];
-  pull<K, SOLIDS>(src, flags, g, n, ph.inv_scale, f);
+#pragma unroll
+  for (int i = 0; i < Q; ++i)
+    f[i] = Storage<K>::load(src[size_t(i) * g.plane + src_off(n, i)], ph.inv_scale);
+  if (SOLIDS && (own & FLAG_SOLID)) return;  // obstacle cells are never written
   C Fx = ph.F[0], Fy = ph.F[1], Fz = ph.F[2];
   if (SOLIDS && FORCE && (own & FLAG_NOFORCE)) Fx = Fy = Fz = C(0);
   collide<C, FORCE>(f, ph.omega, Fx, Fy, Fz);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) dst[size_t(i) * g.plane + n.own] = Storage<K>::store(f[i], ph.scale);
+  for (int i = 0; i < Q; ++i) {
+    const T v = Storage<K>::store(f[i], ph.scale);
+    stream_store(dst + size_t(i) * g.plane + n.own, v);
+    if (SOLIDS && i != 0 && into_solid[i])
+      dst[size_t(D3Q19::opp[i]) * g.plane + src_off(n, D3Q19::opp[i])] = v;
+  }
+}
+
+// Rewrites the ghost slots of a grid from its fluid cells (after a grid has
+// been written from outside the step kernel).
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_ghosts(typename Storage<K>::T* __restrict__ grid,
+                                                   const uint8_t* __restrict__ flags, Geo g) {
+  const Loc l = locate(g);
+  if (!l.valid) return;
+  const Nbhd n = neighbourhood(g, l);
+  if (flags[n.fown] & FLAG_SOLID) return;
+#pragma unroll
+  for (int i = 1; i < Q; ++i)
+    if (flags[src_foff(n, D3Q19::opp[i])] & FLAG_SOLID)
+      grid[size_t(D3Q19::opp[i]) * g.plane + src_off(n, D3Q19::opp[i])] =
+          grid[size_t(i) * g.plane + n.own];
 }
 
 // ---------------------------------------------------------------------------
@@ -254,12 +274,13 @@ __global__ __launch_bounds__(kBlock) void k_init(typename Storage<K>::T* __restr
                                                  const float* __restrict__ u0, Geo g,
                                                  Phys<typename Storage<K>::C> ph) {
   using C = typename Storage<K>::C;
+  using T = typename Storage<K>::T;
   const Loc l = locate(g);
   if (!l.valid) return;
-  const uint32_t c = uint32_t((l.z * g.ny + l.y) * g.nx + l.x);
+  const Nbhd n = neighbourhood(g, l);
+  const uint32_t c = n.fown;
   if (flags && (flags[c] & FLAG_SOLID)) return;
   const size_t ncell = size_t(g.nx) * g.ny * g.nz;
-  const uint32_t own = uint32_t(l.z * g.ny + l.y) * uint32_t(g.xs) + uint32_t(l.x);
   const C rho = rho0 ? C(rho0[c]) : C(1);
   C ux = C(0), uy = C(0), uz = C(0);
   if (u0) {
@@ -271,15 +292,23 @@ __global__ __launch_bounds__(kBlock) void k_init(typename Storage<K>::T* __restr
   const C drho = rho - C(1);
   const C jx = rho * ux, jy = rho * uy, jz = rho * uz;
   const C base = drho - C(1.5) * (jx * ux + jy * uy + jz * uz);
-  grid[own] = Storage<K>::store(coef_W<C>(0) * base, ph.scale);
+  C f[Q];
+  f[0] = coef_W<C>(0) * base;
 #pragma unroll
   for (int k = 1; k < Q; k += 2) {
     const C ej = cdot<C>(k, jx, jy, jz);
     const C eu = cdot<C>(k, ux, uy, uz);
     const C sym = coef_W<C>(k) * base + coef_c<C>(k) * ej * eu;
     const C anti = coef_a<C>(k) * ej;
-    grid[size_t(k) * g.plane + own] = Storage<K>::store(sym + anti, ph.scale);
-    grid[size_t(k + 1) * g.plane + own] = Storage<K>::store(sym - anti, ph.scale);
+    f[k] = sym + anti;
+    f[k + 1] = sym - anti;
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const T v = Storage<K>::store(f[i], ph.scale);
+    grid[size_t(i) * g.plane + n.own] = v;
+    if (flags && i != 0 && (flags[src_foff(n, D3Q19::opp[i])] & FLAG_SOLID))
+      grid[size_t(D3Q19::opp[i]) * g.plane + src_off(n, D3Q19::opp[i])] = v;
   }
 }
 
@@ -611,15 +640,12 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero_bytes(uint8_t* __restrict_
   if (i < n) p[i] = 0;
 }
 
-// STREAM copy c = a: four 16-byte elements per thread, coalesced.
+// STREAM copy c = a: one 16-byte element per thread (more waves in flight
+// measured faster than several elements per thread).
 __global__ __launch_bounds__(kBlock) void k_copy(uint4* __restrict__ c, const uint4* __restrict__ a,
                                                  size_t n16) {
-  const size_t base = size_t(blockIdx.x) * (kBlock * 4) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const size_t i = base + size_t(k) * kBlock;
-    if (i < n16) c[i] = a[i];
-  }
+  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n16) c[i] = a[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -656,6 +682,23 @@ hipError_t launch_init(int storage, const Geo& g, const PhysParams& ph, void* gr
     case ST_F16: init_t<ST_F16>(g, ph, grid, flags, rho0, u0, s); break;
     case ST_BF16: init_t<ST_BF16>(g, ph, grid, flags, rho0, u0, s); break;
     case ST_F64: init_t<ST_F64>(g, ph, grid, flags, rho0, u0, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int K>
+static void ghosts_t(const Geo& g, void* grid, const uint8_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_ghosts<K>, dim3(g.nblocks), dim3(kBlock), 0, s,
+                     reinterpret_cast<typename Storage<K>::T*>(grid), flags, g);
+}
+
+hipError_t launch_ghosts(int storage, const Geo& g, void* grid, const uint8_t* flags, hipStream_t s) {
+  switch (storage) {
+    case ST_F32: ghosts_t<ST_F32>(g, grid, flags, s); break;
+    case ST_F16: ghosts_t<ST_F16>(g, grid, flags, s); break;
+    case ST_BF16: ghosts_t<ST_BF16>(g, grid, flags, s); break;
+    case ST_F64: ghosts_t<ST_F64>(g, grid, flags, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -779,7 +822,7 @@ hipError_t launch_adj_finish(const Geo& g, const double* partials, double* out3,
 }
 
 hipError_t launch_copy(void* c, const void* a, size_t n16, hipStream_t s) {
-  const size_t blocks = (n16 + kBlock * 4 - 1) / (kBlock * 4);
+  const size_t blocks = (n16 + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_copy, dim3(unsigned(blocks)), dim3(kBlock), 0, s,
                      reinterpret_cast<uint4*>(c), reinterpret_cast<const uint4*>(a), n16);
   return hipGetLastError();

@@ -39,7 +39,25 @@ def f_to_grid(sim, f, offsets=False, flags=None):
     nz, ny, nx = sim.shape
     view = sim.populations()
     view[..., :nx].copy_(torch.from_numpy(g).to(view.dtype))
+    sim.refresh_ghosts()
     torch.cuda.synchronize()
+
+
+def check_ghosts(sim, flags, grid=None):
+    """Every solid slot is either the ghost copy g_opp(i)(s + c_i) of a fluid
+    neighbour or 0 (fluid and padding aside); returns the fluid-only offsets."""
+    e, _, opp = R.e_w_opp()
+    g = grid_to_f(sim, grid, offsets=True)
+    solid = (flags & 1) == 1
+    for i in range(1, 19):
+        # value of cell s + c_i, slot opp(i), seen at s
+        nb = np.roll(g[opp[i]], shift=(-e[i, 2], -e[i, 1], -e[i, 0]), axis=(0, 1, 2))
+        nb_fluid = np.roll(~solid, shift=(-e[i, 2], -e[i, 1], -e[i, 0]), axis=(0, 1, 2))
+        want = np.where(nb_fluid, nb, 0.0)
+        assert np.array_equal(g[i][solid], want[solid]), f"ghost slot {i}"
+    assert not g[0][solid].any()
+    g[:, solid] = 0.0
+    return g
 
 
 def rel_linf(a, b, mask=None):

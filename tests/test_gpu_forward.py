@@ -12,7 +12,8 @@ import torch
 from oracle import oracle as O
 from paper_1112_0850_amd import inputs as I
 from paper_1112_0850_amd.lbm import LBM
-from tests.gpu_util import f_to_grid, grid_to_f, rel_linf, say
+from tests import lattice_ref as R
+from tests.gpu_util import check_ghosts, f_to_grid, grid_to_f, rel_linf, say
 
 pytestmark = pytest.mark.gpu
 
@@ -41,7 +42,7 @@ def test_pure_streaming_bit_exact(storage, shape):
     f_to_grid(sim, g, offsets=True, flags=flags)
     for n in (1, 2):
         sim.step(1)
-        got = grid_to_f(sim, offsets=True)
+        got = check_ghosts(sim, flags)
         ref = O.stream(g, flags, n=n)
         assert np.array_equal(got, ref), f"step {n}"
 
@@ -64,8 +65,9 @@ def test_free_streaming_closed_form(shape):
 
 @pytest.mark.parametrize("storage", STORAGES)
 def test_write_coverage_nan_sentinel(storage):
-    """One step writes every fluid slot exactly where expected and never a
-    solid slot or padding: fill the target with NaN, step, inspect."""
+    """One step writes every fluid slot, exactly the ghost slots of solid cells
+    next to fluid (slot i of solid s when s + c_i is fluid), and nothing else:
+    fill the target with NaN, step, inspect."""
     shape = (5, 6, 70)
     say("write coverage", storage, shape)
     flags = I.random_flags(shape, 23, solid_fraction=0.3, noforce_fraction=0.1)
@@ -76,10 +78,19 @@ def test_write_coverage_nan_sentinel(storage):
     torch.cuda.synchronize()
     v = sim.grid_view(dst).to(torch.float64).cpu().numpy()
     nx = shape[2]
+    e = R.e_w_opp()[0]
     fluid = (flags & 1) == 0
-    assert np.isfinite(v[..., :nx][:, fluid]).all()
-    assert np.isnan(v[..., :nx][:, ~fluid]).all()
+    expect = np.zeros((19,) + shape, bool)
+    expect[:, fluid] = True
+    for i in range(1, 19):
+        nb_fluid = np.roll(fluid, shift=(-e[i, 2], -e[i, 1], -e[i, 0]), axis=(0, 1, 2))
+        expect[i] |= (~fluid) & nb_fluid
+    written = np.isfinite(v[..., :nx])
+    assert np.array_equal(written, expect)
     assert np.isnan(v[..., nx:]).all()
+    view = sim.grid_view(dst)
+    view.copy_(torch.nan_to_num(view, nan=0.0))  # untouched slots -> 0
+    check_ghosts(sim, flags, dst)
 
 
 def _run_pair(shape, tau, F, storage, flags, u0, steps, s=0):
@@ -156,6 +167,7 @@ def test_porous_parity(storage, tol):
     sim, f = _run_pair(shape, 0.55, (1e-6, 0, 0), storage, flags, u0, 100, s=s)
     e_rho, e_u, _ = _macro_errors(sim, f, (1e-6, 0, 0), flags)
     say(f"  rel L-inf rho {e_rho:.2e}  u {e_u:.2e}")
+    check_ghosts(sim, flags)
     if tol is None:
         assert e_u <= 5e-2  # stated, not pinned
     else:
