@@ -28,13 +28,13 @@
  *      LBM_F16  IEEE binary16 holding 2^s * g, s = f16_scale_log2.
  *    Every store rounds to nearest-even.  Collision arithmetic is FP32 for
  *    F32/F16/BF16 storage and FP64 for F64 storage.
- *    Solid cells carry no state of their own; their slots serve as ghost
- *    slots of the bounce-back: slot i of a solid cell s holds a copy of
- *    g_opp(i) of the fluid cell s + c_i (when that cell is fluid), so that
- *    the pull of that cell reads its bounced value at the plain shifted
- *    address.  Every other solid slot and all padding stay 0.  The library
- *    maintains the ghost slots itself (init, step, save/restore); after
- *    writing a grid from outside, call lbm_refresh_ghosts.
+ *    Solid cells carry no state of their own: every slot of a solid cell
+ *    holds a quiet-NaN marker (rewritten each step by the cell's own
+ *    thread).  A pull that reads the marker takes the half-way bounce-back
+ *    value from the pulling cell's own opposite slot instead.  Padding
+ *    stays 0.  The library maintains the markers itself (init, step,
+ *    save/restore); after writing a grid from outside, call
+ *    lbm_refresh_solids.  Fluid values must never be NaN.
  *  - Scalar fields are [nz][ny][nx], vector fields [3][nz][ny][nx] (no
  *    padding).  flags are uint8 [nz][ny][nx]: bit0 LBM_FLAG_SOLID (obstacle
  *    cell, never read or written), bit1 LBM_FLAG_NOFORCE (fluid cell without
@@ -113,7 +113,8 @@ void lbm_lattice(int32_t* e, double* w, int32_t* opp);
 
 /* Creates a context over caller-owned memory and enqueues the initial state
  * f*(0) = f^eq(rho0, u0) (Sec. 2 step 2 equilibrium) on fluid cells of
- * grid_a; solid cells and padding of both grids are set to 0.
+ * grid_a, the solid markers on its solid cells; everything else of both
+ * grids (padding included) is set to 0.
  *   grid_a, grid_b  two grids of grid_bytes (the two lattices of Sec. 2);
  *   flags           uint8 [nz][ny][nx] or NULL (all fluid);
  *   scratch         scratch_bytes of device memory for lbm_reduce;
@@ -163,10 +164,10 @@ int64_t lbm_time(const lbm_ctx* ctx);
 lbm_status lbm_set_current(lbm_ctx* ctx, int32_t parity, int64_t t);
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
 
-/* Rewrites the ghost slots of the current grid from its fluid cells (needed
- * only after the caller has written populations into a grid directly).
- * No-op without flags.  Errors: LBM_E_ARG, LBM_E_HIP. */
-lbm_status lbm_refresh_ghosts(lbm_ctx* ctx);
+/* Rewrites the solid markers of the current grid (needed only after the
+ * caller has written populations into a grid directly).  No-op without
+ * flags.  Errors: LBM_E_ARG, LBM_E_HIP. */
+lbm_status lbm_refresh_solids(lbm_ctx* ctx);
 
 /* Device-to-device copy of the current grid to `dst` (lbm_save), or of `src`
  * into the current grid with time t (lbm_restore); grid_bytes each, enqueued

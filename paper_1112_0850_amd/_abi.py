@@ -47,7 +47,7 @@ _SIGNATURES = {
     "lbm_time": (C.c_int64, [_vp]),
     "lbm_set_current": (_st, [_vp, C.c_int32, C.c_int64]),
     "lbm_set_stream": (_st, [_vp, _vp]),
-    "lbm_refresh_ghosts": (_st, [_vp]),
+    "lbm_refresh_solids": (_st, [_vp]),
     "lbm_save": (_st, [_vp, _vp]),
     "lbm_restore": (_st, [_vp, _vp, C.c_int64]),
     "lbm_adjoint_seed": (_st, [_vp, _vp, _vp, _vp, _vp]),
@@ -161,8 +161,8 @@ def lbm_set_stream(ctx, stream):
     check(lib().lbm_set_stream(ctx, stream))
 
 
-def lbm_refresh_ghosts(ctx):
-    check(lib().lbm_refresh_ghosts(ctx))
+def lbm_refresh_solids(ctx):
+    check(lib().lbm_refresh_solids(ctx))
 
 
 def lbm_save(ctx, dst):

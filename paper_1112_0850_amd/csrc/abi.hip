@@ -235,12 +235,13 @@ lbm_status lbm_reduce(lbm_ctx* c, double* out5) {
   return e == hipSuccess ? LBM_OK : hip_fail(e, "reduction launch");
 }
 
-lbm_status lbm_refresh_ghosts(lbm_ctx* c) {
+lbm_status lbm_refresh_solids(lbm_ctx* c) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
   if (!c->flags) return LBM_OK;
-  hipError_t e = lbm::launch_ghosts(c->p.storage, c->geo, c->grid[c->cur], c->flags, c->stream);
-  return e == hipSuccess ? LBM_OK : hip_fail(e, "ghost refresh launch");
+  hipError_t e =
+      lbm::launch_mark_solids(c->p.storage, c->geo, c->grid[c->cur], c->flags, c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "solid marker launch");
 }
 
 int32_t lbm_current(const lbm_ctx* c) { return c ? c->cur : -1; }

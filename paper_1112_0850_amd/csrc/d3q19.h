@@ -109,19 +109,14 @@ struct Storage<ST_F16> {
   __device__ static T store(C v, C scale) { return T(v * scale); }
 };
 
-// bfloat16: the top 16 bits of the binary32 pattern, rounded to nearest-even
-// on store (NaNs stay quiet NaNs).
+// bfloat16: the top 16 bits of the binary32 pattern; the conversion is the
+// hardware's round-to-nearest-even.
 template <>
 struct Storage<ST_BF16> {
-  using T = uint16_t;
+  using T = __bf16;
   using C = float;
-  __device__ static C load(T v, C) { return __uint_as_float(uint32_t(v) << 16); }
-  __device__ static T store(C v, C) {
-    uint32_t u = __float_as_uint(v);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return T((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return T(u >> 16);
-  }
+  __device__ static C load(T v, C) { return float(v); }
+  __device__ static T store(C v, C) { return T(v); }
 };
 
 }  // namespace lbm

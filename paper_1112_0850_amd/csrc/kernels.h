@@ -36,7 +36,8 @@ Geo make_geo(int nx, int ny, int nz, int xs);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_init(int storage, const Geo& g, const PhysParams& ph, void* grid,
                        const uint8_t* flags, const float* rho0, const float* u0, hipStream_t s);
-hipError_t launch_ghosts(int storage, const Geo& g, void* grid, const uint8_t* flags, hipStream_t s);
+hipError_t launch_mark_solids(int storage, const Geo& g, void* grid, const uint8_t* flags,
+                              hipStream_t s);
 hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
                        const void* src, void* dst, const uint8_t* flags, hipStream_t s);
 hipError_t launch_macro(int storage, bool out_f64, const Geo& g, const PhysParams& ph,

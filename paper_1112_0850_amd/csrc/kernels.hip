@@ -120,6 +120,21 @@ __device__ __forceinline__ uint32_t src_foff(const Nbhd& n, int i) {
   return n.frow[1 - D3Q19::cz[i]][1 - D3Q19::cy[i]] + n.xn[D3Q19::cx[i] + 1];
 }
 
+// Population element (i, off): a wave-uniform base of direction array i plus
+// a 32-bit per-lane byte offset (one direction array is < 4 GiB), which maps
+// onto the scalar-base + 32-bit-offset form of global loads and stores and
+// keeps 64-bit address arithmetic out of the per-lane registers.
+template <typename T>
+__device__ __forceinline__ T* elem(T* grid, size_t plane_bytes, int i, uint32_t off) {
+  char* b = reinterpret_cast<char*>(grid) + size_t(i) * plane_bytes;
+  return reinterpret_cast<T*>(b + off * uint32_t(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ const T* elem(const T* grid, size_t plane_bytes, int i, uint32_t off) {
+  const char* b = reinterpret_cast<const char*>(grid) + size_t(i) * plane_bytes;
+  return reinterpret_cast<const T*>(b + off * uint32_t(sizeof(T)));
+}
+
 // c_i . (x, y, z) without multiplications by the constant components (the
 // -0.0 start folds away exactly under IEEE rules).
 template <typename C>
@@ -151,117 +166,158 @@ __device__ __forceinline__ C inv_rho_factor(C drho) {
   return drho / (C(1) + drho);
 }
 
-// BGK relaxation towards the Qian equilibrium with Guo forcing, in place.
-// Offset form with rho never formed:  j' = j + F/2 = rho u,
+// t = drho / (S + drho) for the step kernel.  FP32 uses the hardware
+// reciprocal (1 ulp): t ~ drho is a small correction, so its relative error
+// reaches u only at the level of drho * 2^-23.
+__device__ __forceinline__ float step_t_factor(float drho, float S) {
+  return drho * __builtin_amdgcn_rcpf(S + drho);
+}
+__device__ __forceinline__ double step_t_factor(double drho, double S) {
+  return drho / (S + drho);
+}
+
+// Uniform constants of the fused step, computed once on the host in the
+// compute precision.  Populations are handled in storage units g' = S g
+// (S = 2^s for FP16 storage, 1 otherwise); every term below is linear in g'
+// except u, which is formed unscaled, so the result equals the unscaled
+// computation scaled by the exact power of two S.  Classes: 0 rest,
+// 1 axis, 2 diagonal; pairs p = 0..8 are directions (2p+1, 2p+2) = (c, -c).
+template <typename C>
+struct StepK {
+  C omega, om1;  // omega = 1/tau, 1 - omega
+  C oW[3];       // omega W                 (equilibrium, delta_rho - 3/2 j.u part)
+  C oc[3];       // omega c (exact)         (equilibrium, (c.j)(c.u) part)
+  C a[3];        // a                       (equilibrium, c.j part; multiplied by omega)
+  C S, invS;     // storage scale and its inverse
+  C Fh[3];       // S F / 2                 (j' = j + F/2)
+  C F[3];        // F                       (u.F)
+  C K3W[3];      // 3 (1 - omega/2) W S     (Guo, -3 W u.F part)
+  C Kq[9];       // (1 - omega/2) q (c.F) S (Guo, 9 W (c.u)(c.F) part)
+  C Ka[9];       // (1 - omega/2) a (c.F) S (Guo, 3 W c.F part)
+};
+
+// BGK relaxation towards the Qian equilibrium with Guo forcing, in place, in
+// offset form with rho never formed (j' = j + F/2 = rho u):
 //   g^eq_i = W_i (drho - 3/2 j'.u) + c_i (c_i.j')(c_i.u) +- a_i (c_i.j')
-// (coefficients in Coef<C>), g*_i = (1 - omega) g_i + omega g^eq_i + S_i.
-template <typename C, bool FORCE>
-__device__ __forceinline__ void collide(C* f, C omega, C Fx, C Fy, C Fz) {
-  C drho, jx, jy, jz;
-  moments(f, drho, jx, jy, jz);
+//   S_i    = (1 - omega/2) [q_i (c_i.u)(c_i.F) - 3 W_i u.F +- a_i (c_i.F)]
+//   g*_i   = (1 - omega) g_i + omega g^eq_i + S_i.
+// The momentum-carrying term is omega * (a_i c_i.j') with the conservation-
+// exact a_i, so the collision keeps sum g* c = j + F without a rounding bias
+// from the constants.  `fon` is 1 (forced cell) or 0 (no-force cell).
+template <typename C, bool FORCE, bool SCALED>
+__device__ __forceinline__ void collide(C* f, const StepK<C>& k, C fon) {
+  const C d1 = f[1] - f[2], d3 = f[3] - f[4], d5 = f[5] - f[6], d7 = f[7] - f[8],
+          d9 = f[9] - f[10], d11 = f[11] - f[12], d13 = f[13] - f[14], d15 = f[15] - f[16],
+          d17 = f[17] - f[18];
+  const C drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) +
+                 ((f[8] + f[9]) + (f[10] + f[11])) + ((f[12] + f[13]) + (f[14] + f[15])) +
+                 ((f[16] + f[17]) + f[18]);
+  C jx = ((d1 + d7) + (d9 + d11)) + d13;
+  C jy = ((d3 + d7) - (d9 - d15)) + d17;
+  C jz = ((d5 + d11) - (d13 - d15)) - d17;
   if (FORCE) {
-    jx += C(0.5) * Fx;
-    jy += C(0.5) * Fy;
-    jz += C(0.5) * Fz;
+    jx += fon * k.Fh[0];
+    jy += fon * k.Fh[1];
+    jz += fon * k.Fh[2];
   }
-  const C t = inv_rho_factor(drho);
-  const C ux = jx - jx * t, uy = jy - jy * t, uz = jz - jz * t;
+  const C t = step_t_factor(drho, SCALED ? k.S : C(1));
+  C ux = jx - jx * t, uy = jy - jy * t, uz = jz - jz * t;
+  if (SCALED) {
+    ux *= k.invS;
+    uy *= k.invS;
+    uz *= k.invS;
+  }
   const C base = drho - C(1.5) * (jx * ux + jy * uy + jz * uz);
-  const C om1 = C(1) - omega;
-  const C fpre = C(1) - C(0.5) * omega;
-  const C uF = FORCE ? (ux * Fx + uy * Fy + uz * Fz) : C(0);
-  {
-    C v = om1 * f[0] + omega * (coef_W<C>(0) * base);
-    if (FORCE) v += fpre * (C(-3) * coef_W<C>(0) * uF);
-    f[0] = v;
-  }
+  C uF = C(0);
+  if (FORCE) uF = fon * (ux * k.F[0] + uy * k.F[1] + uz * k.F[2]);
+  C oWb[3];
 #pragma unroll
-  for (int k = 1; k < Q; k += 2) {  // pair (k, k+1) = (c, -c)
-    const C ej = cdot<C>(k, jx, jy, jz);
-    const C eu = cdot<C>(k, ux, uy, uz);
-    const C sym = coef_W<C>(k) * base + coef_c<C>(k) * ej * eu;
-    const C anti = coef_a<C>(k) * ej;
-    C a = om1 * f[k] + omega * (sym + anti);
-    C b = om1 * f[k + 1] + omega * (sym - anti);
+  for (int c = 0; c < 3; ++c) oWb[c] = FORCE ? k.oW[c] * base - k.K3W[c] * uF : k.oW[c] * base;
+  f[0] = k.om1 * f[0] + oWb[0];
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    const int i = 2 * p + 1, c = speed_class(i);
+    const C ej = cdot<C>(i, jx, jy, jz);
+    const C eu = cdot<C>(i, ux, uy, uz);
+    C sym = k.oc[c] * (ej * eu) + oWb[c];
+    C anti = k.omega * (k.a[c] * ej);
     if (FORCE) {
-      const C cF = cdot<C>(k, Fx, Fy, Fz);
-      const C ssym = fpre * (coef_q<C>(k) * eu * cF - C(3) * coef_W<C>(k) * uF);
-      const C santi = fpre * (coef_a<C>(k) * cF);
-      a += ssym + santi;
-      b += ssym - santi;
+      sym += k.Kq[p] * (fon * eu);
+      anti += fon * k.Ka[p];
     }
-    f[k] = a;
-    f[k + 1] = b;
+    f[i] = k.om1 * f[i] + (sym + anti);
+    f[i + 1] = k.om1 * f[i + 1] + (sym - anti);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Fused stream-collide step.
 //
-// Half-way bounce-back through ghost slots: a fluid cell x whose link i
-// points into a solid cell s = x + c_i stores f*_i(x) both in its own slot i
-// and in slot opp(i) of s.  The next step's pull of x in direction opp(i)
-// reads the source x - c_opp(i) = s, slot opp(i), which is f*_i(x) -- the
-// half-way bounce-back value f_opp(i)(x) = f*_i(x).  Every pull therefore
-// loads x - c_i unconditionally, with no flag test between the flag loads and
-// the population loads; the flags are consumed only by the stores.  Each
-// ghost slot has exactly one writer (s - c_i), so steps stay race-free.  The
-// pulls of solid cells are issued speculatively (their lanes stop after the
-// loads) so that no load waits for the cell's own flag.
+// Half-way bounce-back through solid markers: every slot of a solid cell
+// holds a quiet NaN, rewritten by the solid cell's own lane each step.  Each
+// lane pulls x - c_i for all i unconditionally; a pull that lands on a solid
+// cell returns the marker, and only then does the lane load the half-way
+// bounce-back value f*_opp(i)(x) from its own cell.  So no population load
+// waits for geometry, and every lane -- fluid or solid -- stores all 19 of
+// its own slots, which keeps every store instruction a full, coalesced line
+// (partially written lines cost far more HBM time than their bytes).  The
+// flags are read only for the solid test and the per-cell force switch.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void stream_store(T* p, T v) {
   __builtin_nontemporal_store(v, p);
 }
 
+template <typename C>
+__device__ __forceinline__ bool is_marker(C v) {
+  return v != v;  // NaN
+}
+
 template <int K, bool SOLIDS, bool FORCE>
 __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* __restrict__ src,
                                                  typename Storage<K>::T* __restrict__ dst,
                                                  const uint8_t* __restrict__ flags, Geo g,
-                                                 Phys<typename Storage<K>::C> ph) {
+                                                 StepK<typename Storage<K>::C> k) {
   using C = typename Storage<K>::C;
   using T = typename Storage<K>::T;
+  constexpr bool SCALED = (K == ST_F16);
   const Loc l = locate(g);
   if (!l.valid) return;
   const Nbhd n = neighbourhood(g, l);
-  uint8_t own = 0;
-  bool into_solid[Q];  // link i points into a solid cell x + c_i (the pull source of opp(i))
-  if (SOLIDS) {
-    own = flags[n.fown];
-#pragma unroll
-    for (int i = 1; i < Q; ++i) into_solid[i] = flags[src_foff(n, D3Q19::opp[i])] & FLAG_SOLID;
-  }
+  const uint8_t fl = SOLIDS ? flags[n.fown] : uint8_t(0);
+  const size_t pb = size_t(g.plane) * sizeof(T);
   C f[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i)
-    f[i] = Storage<K>::load(src[size_t(i) * g.plane + src_off(n, i)], ph.inv_scale);
-  if (SOLIDS && (own & FLAG_SOLID)) return;  // obstacle cells are never written
-  C Fx = ph.F[0], Fy = ph.F[1], Fz = ph.F[2];
-  if (SOLIDS && FORCE && (own & FLAG_NOFORCE)) Fx = Fy = Fz = C(0);
-  collide<C, FORCE>(f, ph.omega, Fx, Fy, Fz);
+  for (int i = 0; i < Q; ++i) f[i] = C(*elem(src, pb, i, src_off(n, i)));
+  const bool solid = SOLIDS && (fl & FLAG_SOLID);
+  if (SOLIDS) {
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const T v = Storage<K>::store(f[i], ph.scale);
-    stream_store(dst + size_t(i) * g.plane + n.own, v);
-    if (SOLIDS && i != 0 && into_solid[i])
-      dst[size_t(D3Q19::opp[i]) * g.plane + src_off(n, D3Q19::opp[i])] = v;
+    for (int i = 1; i < Q; ++i)
+      if (is_marker(f[i]) && !solid) f[i] = C(*elem(src, pb, D3Q19::opp[i], n.own));
   }
+  // Solid lanes run the collision on their (meaningless) pulls and discard it.
+  if (FORCE && SOLIDS)
+    collide<C, FORCE, SCALED>(f, k, (fl & FLAG_NOFORCE) ? C(0) : C(1));
+  else
+    collide<C, FORCE, SCALED>(f, k, C(1));
+  const C marker = C(__builtin_nan(""));
+#pragma unroll
+  for (int i = 0; i < Q; ++i) stream_store(elem(dst, pb, i, n.own), T(solid ? marker : f[i]));
 }
 
-// Rewrites the ghost slots of a grid from its fluid cells (after a grid has
-// been written from outside the step kernel).
+// Writes the solid marker into every slot of the solid cells of a grid.
 template <int K>
-__global__ __launch_bounds__(kBlock) void k_ghosts(typename Storage<K>::T* __restrict__ grid,
-                                                   const uint8_t* __restrict__ flags, Geo g) {
+__global__ __launch_bounds__(kBlock) void k_mark_solids(typename Storage<K>::T* __restrict__ grid,
+                                                        const uint8_t* __restrict__ flags, Geo g) {
+  using T = typename Storage<K>::T;
+  using C = typename Storage<K>::C;
   const Loc l = locate(g);
   if (!l.valid) return;
   const Nbhd n = neighbourhood(g, l);
-  if (flags[n.fown] & FLAG_SOLID) return;
+  if (!(flags[n.fown] & FLAG_SOLID)) return;
+  const size_t pb = size_t(g.plane) * sizeof(T);
 #pragma unroll
-  for (int i = 1; i < Q; ++i)
-    if (flags[src_foff(n, D3Q19::opp[i])] & FLAG_SOLID)
-      grid[size_t(D3Q19::opp[i]) * g.plane + src_off(n, D3Q19::opp[i])] =
-          grid[size_t(i) * g.plane + n.own];
+  for (int i = 0; i < Q; ++i) *elem(grid, pb, i, n.own) = T(C(__builtin_nan("")));
 }
 
 // ---------------------------------------------------------------------------
@@ -279,7 +335,12 @@ __global__ __launch_bounds__(kBlock) void k_init(typename Storage<K>::T* __restr
   if (!l.valid) return;
   const Nbhd n = neighbourhood(g, l);
   const uint32_t c = n.fown;
-  if (flags && (flags[c] & FLAG_SOLID)) return;
+  const size_t pb = size_t(g.plane) * sizeof(T);
+  if (flags && (flags[c] & FLAG_SOLID)) {  // solid marker
+#pragma unroll
+    for (int i = 0; i < Q; ++i) *elem(grid, pb, i, n.own) = T(C(__builtin_nan("")));
+    return;
+  }
   const size_t ncell = size_t(g.nx) * g.ny * g.nz;
   const C rho = rho0 ? C(rho0[c]) : C(1);
   C ux = C(0), uy = C(0), uz = C(0);
@@ -304,12 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_init(typename Storage<K>::T* __restr
     f[k + 1] = sym - anti;
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    const T v = Storage<K>::store(f[i], ph.scale);
-    grid[size_t(i) * g.plane + n.own] = v;
-    if (flags && i != 0 && (flags[src_foff(n, D3Q19::opp[i])] & FLAG_SOLID))
-      grid[size_t(D3Q19::opp[i]) * g.plane + src_off(n, D3Q19::opp[i])] = v;
-  }
+  for (int i = 0; i < Q; ++i) *elem(grid, pb, i, n.own) = Storage<K>::store(f[i], ph.scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -688,20 +744,51 @@ hipError_t launch_init(int storage, const Geo& g, const PhysParams& ph, void* gr
 }
 
 template <int K>
-static void ghosts_t(const Geo& g, void* grid, const uint8_t* flags, hipStream_t s) {
-  hipLaunchKernelGGL(k_ghosts<K>, dim3(g.nblocks), dim3(kBlock), 0, s,
+static void mark_t(const Geo& g, void* grid, const uint8_t* flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_mark_solids<K>, dim3(g.nblocks), dim3(kBlock), 0, s,
                      reinterpret_cast<typename Storage<K>::T*>(grid), flags, g);
 }
 
-hipError_t launch_ghosts(int storage, const Geo& g, void* grid, const uint8_t* flags, hipStream_t s) {
+hipError_t launch_mark_solids(int storage, const Geo& g, void* grid, const uint8_t* flags,
+                              hipStream_t s) {
   switch (storage) {
-    case ST_F32: ghosts_t<ST_F32>(g, grid, flags, s); break;
-    case ST_F16: ghosts_t<ST_F16>(g, grid, flags, s); break;
-    case ST_BF16: ghosts_t<ST_BF16>(g, grid, flags, s); break;
-    case ST_F64: ghosts_t<ST_F64>(g, grid, flags, s); break;
+    case ST_F32: mark_t<ST_F32>(g, grid, flags, s); break;
+    case ST_F16: mark_t<ST_F16>(g, grid, flags, s); break;
+    case ST_BF16: mark_t<ST_BF16>(g, grid, flags, s); break;
+    case ST_F64: mark_t<ST_F64>(g, grid, flags, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// Host-side construction of the uniform step constants (see StepK).
+template <typename C>
+static StepK<C> make_stepk(const PhysParams& p) {
+  StepK<C> k;
+  const double om = p.omega, fpre = 1.0 - 0.5 * om, S = p.scale;
+  k.omega = C(om);
+  k.om1 = C(1) - k.omega;
+  const int rep[3] = {0, 1, 7};  // a direction of each speed class
+  for (int c = 0; c < 3; ++c) {
+    const int i = rep[c];
+    k.oW[c] = C(om * weight<double>(i));
+    k.oc[c] = c ? k.omega * coef_c<C>(i) : C(0);  // exact: c is 1/4 or 1/8
+    k.a[c] = c ? coef_a<C>(i) : C(0);
+    k.K3W[c] = C(3.0 * fpre * weight<double>(i) * S);
+  }
+  k.S = C(S);
+  k.invS = C(1.0 / S);
+  for (int d = 0; d < 3; ++d) {
+    k.Fh[d] = C(0.5 * S * p.F[d]);
+    k.F[d] = C(p.F[d]);
+  }
+  for (int q = 0; q < 9; ++q) {
+    const int i = 2 * q + 1;
+    const double cF = D3Q19::cx[i] * p.F[0] + D3Q19::cy[i] * p.F[1] + D3Q19::cz[i] * p.F[2];
+    k.Kq[q] = C(fpre * 9.0 * weight<double>(i) * cF * S);
+    k.Ka[q] = C(fpre * 3.0 * weight<double>(i) * cF * S);
+  }
+  return k;
 }
 
 template <int K, bool SOLIDS, bool FORCE>
@@ -711,7 +798,7 @@ static void step_t(const Geo& g, const PhysParams& ph, const void* src, void* ds
   hipLaunchKernelGGL((k_step<K, SOLIDS, FORCE>), dim3(g.nblocks), dim3(kBlock), 0, s,
                      reinterpret_cast<const typename S::T*>(src),
                      reinterpret_cast<typename S::T*>(dst), flags, g,
-                     to_phys<typename S::C>(ph));
+                     make_stepk<typename S::C>(ph));
 }
 
 template <int K>

@@ -123,10 +123,10 @@ class LBM:
     def restore(self, src, t):
         A.lbm_restore(self.ctx, _ptr(src), t)
 
-    def refresh_ghosts(self):
-        """Rewrite the bounce-back ghost slots of the current grid (after
+    def refresh_solids(self):
+        """Rewrite the solid-cell markers of the current grid (after
         populations were written into it directly)."""
-        A.lbm_refresh_ghosts(self.ctx)
+        A.lbm_refresh_solids(self.ctx)
 
     def set_current(self, parity, t):
         A.lbm_set_current(self.ctx, parity, t)

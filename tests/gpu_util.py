@@ -13,16 +13,23 @@ def say(*a):
     print("[gpu-test]", *a, flush=True)
 
 
-def grid_to_f(sim, grid=None, offsets=False):
+def grid_to_f(sim, grid=None, offsets=False, raw=False):
     """The populations of a grid (default: current) as float64 [19, nz, ny, nx];
-    f = g / scale + w unless offsets=True.  Solid cells come back as stored."""
+    f = g / scale + w unless offsets=True.  Solid cells (which hold the
+    library's NaN markers) come back as 0 unless raw=True."""
     g = sim.populations() if grid is None else sim.grid_view(grid)
     nz, ny, nx = sim.shape
     a = g[..., :nx].to(torch.float64).cpu().numpy()
+    solid = None
+    if sim.flags is not None and not raw:
+        solid = (sim.flags.cpu().numpy() & 1) == 1
+        a[:, solid] = 0.0
     if sim.storage == 1:  # FP16 holds 2^s g
         a = a / 2.0 ** sim.params.f16_scale_log2
     if not offsets:
         a = a + W[:, None, None, None]
+        if solid is not None:
+            a[:, solid] = 0.0
     return a
 
 
@@ -39,23 +46,17 @@ def f_to_grid(sim, f, offsets=False, flags=None):
     nz, ny, nx = sim.shape
     view = sim.populations()
     view[..., :nx].copy_(torch.from_numpy(g).to(view.dtype))
-    sim.refresh_ghosts()
+    sim.refresh_solids()
     torch.cuda.synchronize()
 
 
-def check_ghosts(sim, flags, grid=None):
-    """Every solid slot is either the ghost copy g_opp(i)(s + c_i) of a fluid
-    neighbour or 0 (fluid and padding aside); returns the fluid-only offsets."""
-    e, _, opp = R.e_w_opp()
-    g = grid_to_f(sim, grid, offsets=True)
+def check_solids(sim, flags, grid=None):
+    """Every slot of every solid cell holds the NaN marker; returns the
+    offsets with solid cells zeroed (the oracle's convention)."""
+    g = grid_to_f(sim, grid, offsets=True, raw=True)
     solid = (flags & 1) == 1
-    for i in range(1, 19):
-        # value of cell s + c_i, slot opp(i), seen at s
-        nb = np.roll(g[opp[i]], shift=(-e[i, 2], -e[i, 1], -e[i, 0]), axis=(0, 1, 2))
-        nb_fluid = np.roll(~solid, shift=(-e[i, 2], -e[i, 1], -e[i, 0]), axis=(0, 1, 2))
-        want = np.where(nb_fluid, nb, 0.0)
-        assert np.array_equal(g[i][solid], want[solid]), f"ghost slot {i}"
-    assert not g[0][solid].any()
+    assert np.isnan(g[:, solid]).all(), "solid marker missing"
+    assert np.isfinite(g[:, ~solid]).all(), "non-finite fluid population"
     g[:, solid] = 0.0
     return g
 
