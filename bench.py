@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic porous box")
     ap.add_argument("--only", default="", help="comma list of legs: f32,f16,bf16,f64,adjoint,copy,cpu")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="summarise rocprofv3 CSV output (kernel trace, FETCH_SIZE and "
+                         "WRITE_SIZE passes of this script) into profiles/ and exit")
     return ap.parse_args()
 
 
@@ -168,13 +171,13 @@ def cpu_leg(flags_np, seconds):
     crop = np.ascontiguousarray(flags_np[:128, :128, :128])
     shape = crop.shape
     f = O.init(shape, crop)
-    t0 = time.perf_counter()
-    f = O.step(f, 0.55, (1e-6, 0, 0), crop, n=1)
-    t1 = time.perf_counter() - t0
-    nsteps = max(1, int(seconds / max(t1, 1e-3)))
-    t0 = time.perf_counter()
-    O.step(f, 0.55, (1e-6, 0, 0), crop, n=nsteps)
-    dt = time.perf_counter() - t0
+    f = O.step(f, 0.55, (1e-6, 0, 0), crop, n=2)  # warm-up (threads, pages)
+    nsteps, dt = 0, 0.0
+    while dt < seconds:  # whole chunks of 5 steps until the time budget is spent
+        t0 = time.perf_counter()
+        f = O.step(f, 0.55, (1e-6, 0, 0), crop, n=5)
+        dt += time.perf_counter() - t0
+        nsteps += 5
     cells = int(np.prod(shape))
     fluid = int((crop & 1 == 0).sum())
     return {"value": cells * nsteps / dt / 1e6, "unit": "MLUPS", "cores": O.threads(),
@@ -196,8 +199,84 @@ def traffic_entry(alg_bytes, ms):
     return t.get("traffic_bytes_per_launch")
 
 
+KERNELS = {  # kernel-name prefix -> (storage, algorithmic bytes per fluid update)
+    "void lbm::k_step<0, true, true>": ("f32", 152),
+    "void lbm::k_step<1, true, true>": ("f16", 76),
+    "void lbm::k_step<2, true, true>": ("bf16", 76),
+    "void lbm::k_step<3, true, true>": ("f64", 304),
+}
+
+
+def profile_summary(trace_dir, fetch_dir, write_dir, n=512):
+    """Summarise the rocprofv3 runs of this script: average kernel durations,
+    and HBM traffic per dispatch from FETCH_SIZE / WRITE_SIZE (KiB), each
+    calibrated by the same counter on the copy kernel of known size."""
+    import csv
+    import glob
+    import numpy as np
+    from paper_1112_0850_amd import inputs as I
+
+    def one(pattern):
+        hits = glob.glob(os.path.join(pattern))
+        if not hits:
+            raise FileNotFoundError(pattern)
+        return hits[0]
+
+    stats = list(csv.DictReader(open(one(os.path.join(trace_dir, "*kernel_stats.csv")))))
+    counters = {}
+    for d, cname in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
+        for r in csv.DictReader(open(one(os.path.join(d, "*counter_collection.csv")))):
+            if r["Counter_Name"] == cname:
+                counters.setdefault((r["Kernel_Name"], cname), []).append(float(r["Counter_Value"]))
+    copy_name = next(k for k, _ in counters if k.startswith("lbm::k_copy"))
+    copy_bytes = 4 << 30  # the copy leg moves 4 GiB in, 4 GiB out
+    scale = {c: copy_bytes / (1024 * np.mean(counters[(copy_name, c)]))
+             for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    flags = I.sphere_pack((n, n, n), 0.10, seed=12345)
+    n_fluid, n_cells = int((flags & 1 == 0).sum()), n ** 3
+    lines = ["| kernel | calls | avg us | fetch GB | write GB | alg GB | traffic/alg |",
+             "|---|---|---|---|---|---|---|"]
+    record = {}
+    for r in stats:
+        name = r["Name"]
+        avg_us = float(r["AverageNs"]) / 1e3
+        row = [name.split("(")[0][:48], r["Calls"], f"{avg_us:.1f}"]
+        key = next((k for k in KERNELS if name.startswith(k)), None)
+        fk, wk = (name, "FETCH_SIZE"), (name, "WRITE_SIZE")
+        if fk in counters and wk in counters:
+            fb = np.mean(counters[fk]) * 1024 * scale["FETCH_SIZE"]
+            wb = np.mean(counters[wk]) * 1024 * scale["WRITE_SIZE"]
+            row += [f"{fb / 1e9:.2f}", f"{wb / 1e9:.2f}"]
+            if key:
+                st, bpu = KERNELS[key]
+                alg = bpu * n_fluid + n_cells
+                row += [f"{alg / 1e9:.2f}", f"{(fb + wb) / alg:.3f}"]
+                record[st] = {"kernel": key, "avg_us": avg_us, "fetch_bytes": fb,
+                              "write_bytes": wb, "alg_bytes": alg}
+            else:
+                row += ["", ""]
+        else:
+            row += ["", "", "", ""]
+        if float(r["Percentage"]) > 0.05 or key:
+            lines.append("| " + " | ".join(row) + " |")
+    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    out = {"kernels_sha256": src_hash, "fetch_scale": scale["FETCH_SIZE"],
+           "write_scale": scale["WRITE_SIZE"], "kernels": record}
+    if "f32" in record:
+        out["traffic_bytes_per_launch"] = record["f32"]["fetch_bytes"] + record["f32"]["write_bytes"]
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
+    text = "\n".join(lines)
+    print(text)
+    print(f"\ncounter calibration (copy kernel, 4 GiB): FETCH_SIZE x{scale['FETCH_SIZE']:.4f}, "
+          f"WRITE_SIZE x{scale['WRITE_SIZE']:.4f}")
+    return 0
+
+
 def main():
     args = parse()
+    if args.profile_summary:
+        return profile_summary(*args.profile_summary)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "domain decomposition is a design note, not part of this build", file=sys.stderr)
