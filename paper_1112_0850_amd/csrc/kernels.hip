@@ -273,7 +273,16 @@ __device__ __forceinline__ bool is_marker(C v) {
   return v != v;  // NaN
 }
 
-template <int K, bool SOLIDS, bool FORCE>
+// Cells per lane of the step kernel: a wave owns a run of 64*M cells of one
+// row and each lane updates the cells x0 + 64 m, m < M.  More cells
+// per lane put more bytes in flight per wave, which is what the 16-bit
+// storages need to cover memory latency at the occupancy limit.
+template <int K>
+struct StepCells {
+  static constexpr int M = (K == ST_F16 || K == ST_BF16) ? 4 : 1;
+};
+
+template <int K, bool SOLIDS, bool FORCE, int M>
 __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* __restrict__ src,
                                                  typename Storage<K>::T* __restrict__ dst,
                                                  const uint8_t* __restrict__ flags, Geo g,
@@ -281,28 +290,60 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
   using C = typename Storage<K>::C;
   using T = typename Storage<K>::T;
   constexpr bool SCALED = (K == ST_F16);
-  const Loc l = locate(g);
-  if (!l.valid) return;
-  const Nbhd n = neighbourhood(g, l);
-  const uint8_t fl = SOLIDS ? flags[n.fown] : uint8_t(0);
-  const size_t pb = size_t(g.plane) * sizeof(T);
-  C f[Q];
+  // g describes 64*M-cell segments (step_geo); same block remap as locate().
+  const int b = blockIdx.x;
+  const int lb = (b < g.nb8) ? ((b & 7) * (g.nb8 >> 3) + (b >> 3)) : b;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int seg = lb * 4 + wave;
+  const int row = seg / g.nseg;
+  if (row >= g.nrows) return;
+  Loc l;
+  l.z = row / g.ny;
+  l.y = row - l.z * g.ny;
+  const int x0 = (seg - row * g.nseg) * 64 * M + int(threadIdx.x & 63);
+  Nbhd n[M];
+  bool valid[M];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = C(*elem(src, pb, i, src_off(n, i)));
-  const bool solid = SOLIDS && (fl & FLAG_SOLID);
-  if (SOLIDS) {
-#pragma unroll
-    for (int i = 1; i < Q; ++i)
-      if (is_marker(f[i]) && !solid) f[i] = C(*elem(src, pb, D3Q19::opp[i], n.own));
+  for (int m = 0; m < M; ++m) {
+    const int x = x0 + 64 * m;
+    valid[m] = x < g.nx;
+    l.x = valid[m] ? x : g.nx - 1;  // past the row end: load in bounds, store nothing
+    n[m] = neighbourhood(g, l);
   }
-  // Solid lanes run the collision on their (meaningless) pulls and discard it.
-  if (FORCE && SOLIDS)
-    collide<C, FORCE, SCALED>(f, k, (fl & FLAG_NOFORCE) ? C(0) : C(1));
-  else
-    collide<C, FORCE, SCALED>(f, k, C(1));
+  if (!valid[0]) return;
+  uint8_t fl[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) fl[m] = SOLIDS ? flags[n[m].fown] : uint8_t(0);
+  const size_t pb = size_t(g.plane) * sizeof(T);
+  C f[M][Q];
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[m][i] = C(*elem(src, pb, i, src_off(n[m], i)));
+  bool solid[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    solid[m] = SOLIDS && (fl[m] & FLAG_SOLID);
+    if (SOLIDS) {
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        if (is_marker(f[m][i]) && !solid[m]) f[m][i] = C(*elem(src, pb, D3Q19::opp[i], n[m].own));
+    }
+  }
   const C marker = C(__builtin_nan(""));
 #pragma unroll
-  for (int i = 0; i < Q; ++i) stream_store(elem(dst, pb, i, n.own), T(solid ? marker : f[i]));
+  for (int m = 0; m < M; ++m) {
+    // Solid lanes run the collision on their (meaningless) pulls and discard it.
+    if (FORCE && SOLIDS)
+      collide<C, FORCE, SCALED>(f[m], k, (fl[m] & FLAG_NOFORCE) ? C(0) : C(1));
+    else
+      collide<C, FORCE, SCALED>(f[m], k, C(1));
+    if (valid[m]) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        stream_store(elem(dst, pb, i, n[m].own), T(solid[m] ? marker : f[m][i]));
+    }
+  }
 }
 
 // Writes the solid marker into every slot of the solid cells of a grid.
@@ -791,13 +832,25 @@ static StepK<C> make_stepk(const PhysParams& p) {
   return k;
 }
 
+// Geometry of 64*M-cell segments for the step kernel.
+static Geo step_geo(const Geo& g, int M) {
+  Geo h = g;
+  h.nseg = (g.nx + 64 * M - 1) / (64 * M);
+  const int64_t segs = int64_t(h.nseg) * g.nrows;
+  h.nblocks = int32_t((segs + 3) / 4);
+  h.nb8 = (h.nblocks / 8) * 8;
+  return h;
+}
+
 template <int K, bool SOLIDS, bool FORCE>
 static void step_t(const Geo& g, const PhysParams& ph, const void* src, void* dst,
                    const uint8_t* flags, hipStream_t s) {
   using S = Storage<K>;
-  hipLaunchKernelGGL((k_step<K, SOLIDS, FORCE>), dim3(g.nblocks), dim3(kBlock), 0, s,
+  constexpr int M = StepCells<K>::M;
+  const Geo h = step_geo(g, M);
+  hipLaunchKernelGGL((k_step<K, SOLIDS, FORCE, M>), dim3(h.nblocks), dim3(kBlock), 0, s,
                      reinterpret_cast<const typename S::T*>(src),
-                     reinterpret_cast<typename S::T*>(dst), flags, g,
+                     reinterpret_cast<typename S::T*>(dst), flags, h,
                      make_stepk<typename S::C>(ph));
 }
 
