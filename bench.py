@@ -39,8 +39,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic porous box")
-    ap.add_argument("--only", default="", help="comma list of legs: f32,f16,bf16,f64,adjoint,copy,cpu")
+    ap.add_argument("--only", default="",
+                    help="comma list of legs: f32,f16,bf16,f64,f32x,adjoint,copy,cpu,large")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--sweep", action="store_true",
+                    help="domain-size sweep instead of the headline run: periodic all-fluid cubes "
+                         "N^3, padded (x_stride multiple of 64) vs unpadded, FP32/FP16/FP64; "
+                         "prints one JSON line per point")
     ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="summarise rocprofv3 CSV output (kernel trace, FETCH_SIZE and "
                          "WRITE_SIZE passes of this script) into profiles/ and exit")
@@ -81,6 +86,49 @@ def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s
     del sim
     torch.cuda.empty_cache()
     return out
+
+
+def large_leg(torch, storage, n, steps=100, warmup=5):
+    """Large box (5% solid random spheres r 4-12, seed 777, tau 0.55,
+    g_x 1e-6, from rest): sustained MLUPS, bandwidth and FP64 mass drift."""
+    from paper_1112_0850_amd import _abi as A
+    from paper_1112_0850_amd import inputs as I
+    from paper_1112_0850_amd.lbm import LBM
+    flags = I.sphere_pack((n, n, n), 0.05, seed=777)
+    n_cells, n_fluid = n ** 3, int((flags & 1 == 0).sum())
+    sim = LBM((n, n, n), 0.55, (1e-6, 0.0, 0.0), storage, flags=torch.from_numpy(flags).cuda())
+    m0 = float(sim.reduce()[0].item())
+    ms = timed_steps(sim, torch, steps, warmup)
+    m1 = float(sim.reduce()[0].item())
+    bpu = A.lbm_bytes_per_update(sim.storage)
+    alg = bpu * n_fluid + n_cells
+    out = {"workload": f"{n}^3 porous 5% spheres seed 777, {storage}", "grid_gb": 2 * sim.grid_bytes / 1e9,
+           "ms_per_step": ms, "mlups": n_cells / ms / 1e3, "mflups": n_fluid / ms / 1e3,
+           "alg_gbs": alg / ms / 1e6, "hbm_frac": alg / ms / 1e6 / HBM_PEAK_GBS,
+           "mass_drift_rel": abs(m1 - m0) / m0, "steps": steps + warmup}
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+SWEEP_N = (32, 48, 64, 80, 96, 100, 128, 160, 192, 200, 250, 256, 300, 320, 384, 400, 448, 500, 512)
+
+
+def sweep(torch):
+    """MLUPS against the edge N of a periodic all-fluid cube (tau 0.6, no
+    force, at rest), with the x-stride padded to 64 cells or not padded."""
+    from paper_1112_0850_amd.lbm import LBM
+    for st in ("f32", "f16", "f64"):
+        for n in SWEEP_N:
+            for align in (0, 1):
+                sim = LBM((n, n, n), 0.6, (0.0, 0.0, 0.0), st, x_align=align)
+                steps = max(10, min(400, int(2e9 / n ** 3)))
+                ms = timed_steps(sim, torch, steps, max(3, steps // 10))
+                print(json.dumps({"sweep": st, "n": n, "padded": align == 0, "x_stride": sim.x_stride,
+                                  "ms_per_step": ms, "mlups": n ** 3 / ms / 1e3}), flush=True)
+                del sim
+            torch.cuda.empty_cache()
+    return 0
 
 
 def copy_leg(torch):
@@ -285,9 +333,11 @@ def main():
     import torch
     from paper_1112_0850_amd import inputs as I
     from paper_1112_0850_amd.lbm import LBM
+    if args.sweep:
+        return sweep(torch)
 
-    legs = set(args.only.split(",")) if args.only else {"f32", "f16", "bf16", "f64", "adjoint",
-                                                        "copy", "cpu"}
+    legs = set(args.only.split(",")) if args.only else {"f32", "f16", "bf16", "f64", "f32x",
+                                                        "adjoint", "copy", "cpu", "large"}
     n = args.n
     log(f"geometry: {n}^3 sphere pack, 10% solid, seed 12345")
     flags = I.sphere_pack((n, n, n), 0.10, seed=12345)
@@ -298,7 +348,7 @@ def main():
     if "copy" in legs:
         log("copy probe")
         res["copy"] = copy_leg(torch)
-    for st, s in (("f32", 0), ("f16", 12), ("bf16", 0), ("f64", 0)):
+    for st, s in (("f32", 0), ("f16", 12), ("bf16", 0), ("f64", 0), ("f32x", 0)):
         if st in legs:
             log(f"forward {st}")
             res[st] = forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st, args.steps,
@@ -307,11 +357,17 @@ def main():
     if "adjoint" in legs:
         log("adjoint 128^3")
         res["adjoint"] = adjoint_leg(torch)
+    if "large" in legs:
+        del flags_t
+        torch.cuda.empty_cache()
+        log("large 768^3 f32, 640^3 f64")
+        res["large"] = [large_leg(torch, "f32", 768), large_leg(torch, "f64", 640)]
     if "cpu" in legs:
         log("cpu oracle sample")
         res["cpu"] = cpu_leg(flags, args.cpu_seconds)
 
-    main_leg = res.get("f32") or next((res[k] for k in ("f16", "bf16", "f64") if k in res), None)
+    main_leg = res.get("f32") or next((res[k] for k in ("f16", "bf16", "f64", "f32x") if k in res),
+                                      None)
     line = {
         "metric": "MLUPS & %HBM roofline, D3Q19 512^3 FP32 vs FP16-offset; adjoint/fwd time",
         "value": main_leg["mlups"] if main_leg else None,
@@ -319,7 +375,8 @@ def main():
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": main_leg["ms_per_step"] if main_leg else None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"f32": "f32", "f16": "f16", "bf16": "bf16", "f64": "f64"}[main_leg["storage"]]
+        "dtype": {"f32": "f32", "f16": "f32", "bf16": "f32", "f64": "f64",
+                  "f32x": "f64"}[main_leg["storage"]]
         if main_leg else None,
         "data": "synthetic",
         "config": {"workload": f"D3Q19 BGK porous periodic box {n}^3, 10% solid random spheres "
@@ -338,13 +395,15 @@ def main():
     if "cpu" in res:
         line["cpu_baseline"] = res["cpu"]
     line["mflups"] = main_leg["mflups"] if main_leg else None
-    for st in ("f16", "bf16", "f64"):
+    for st in ("f16", "bf16", "f64", "f32x"):
         if st in res:
             line[f"{st}_storage"] = res[st]
     if "f16" in res and "f32" in res:
         line["f16_over_f32"] = res["f16"]["mlups"] / res["f32"]["mlups"]
     if "adjoint" in res:
         line["adjoint"] = res["adjoint"]
+    if "large" in res:
+        line["large"] = res["large"]
     if "copy" in res:
         line["copy_gbs"] = res["copy"]["gbs"]
         if main_leg:

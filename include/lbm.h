@@ -27,7 +27,7 @@
  *      LBM_F32  float,  LBM_F64 double,  LBM_BF16 bfloat16 (g),
  *      LBM_F16  IEEE binary16 holding 2^s * g, s = f16_scale_log2.
  *    Every store rounds to nearest-even.  Collision arithmetic is FP32 for
- *    F32/F16/BF16 storage and FP64 for F64 storage.
+ *    F32/F16/BF16 storage and FP64 for F64 and F32X storage.
  *    Solid cells carry no state of their own: every slot of a solid cell
  *    holds a quiet-NaN marker (rewritten each step by the cell's own
  *    thread).  A pull that reads the marker takes the half-way bounce-back
@@ -75,7 +75,15 @@ typedef enum {
   LBM_E_STATE = -4        /* call not valid for this context's state */
 } lbm_status;
 
-typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2, LBM_F64 = 3 } lbm_storage;
+typedef enum {
+  LBM_F32 = 0,  /* float offsets, FP32 collision arithmetic */
+  LBM_F16 = 1,  /* binary16 holding 2^s offsets, FP32 arithmetic */
+  LBM_BF16 = 2, /* bfloat16 offsets, FP32 arithmetic */
+  LBM_F64 = 3,  /* double offsets, FP64 arithmetic */
+  LBM_F32X = 4  /* float offsets (same layout and bytes as LBM_F32), FP64
+                   collision arithmetic: the accuracy mode for long or slowly
+                   converging runs, where FP32 arithmetic errors accumulate */
+} lbm_storage;
 
 enum { LBM_FLAG_SOLID = 1, LBM_FLAG_NOFORCE = 2 };
 
@@ -177,7 +185,7 @@ lbm_status lbm_restore(lbm_ctx* ctx, const void* src, int64_t t);
 
 /* ---- discrete adjoint (LBM_F32 storage only) ------------------------------
  * Reverse mode of the update above for an objective L of the final
- * macroscopic fields.  lambda^n = dL/d f*(n) is FP32 in the grid layout
+ * macroscopic fields (FP32 or FP32X storage; FP32 adjoint arithmetic).  lambda^n = dL/d f*(n) is FP32 in the grid layout
  * ([19][nz][ny][x_stride] floats); its solid-cell and padding slots must be
  * zero when first used (the seed writes zeros there and the step never
  * writes them).  dL/dF is accumulated per thread block in an FP64 partials

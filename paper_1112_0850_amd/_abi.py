@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_E_ARG, LBM_E_HIP, LBM_E_UNSUPPORTED, LBM_E_STATE = 0, -1, -2, -3, -4
-LBM_F32, LBM_F16, LBM_BF16, LBM_F64 = 0, 1, 2, 3
+LBM_F32, LBM_F16, LBM_BF16, LBM_F64, LBM_F32X = 0, 1, 2, 3, 4
 LBM_FLAG_SOLID, LBM_FLAG_NOFORCE = 1, 2
 
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_HIP", -3: "LBM_E_UNSUPPORTED",

@@ -36,6 +36,7 @@ size_t elem_size(int32_t storage) {
     case LBM_F16: return 2;
     case LBM_BF16: return 2;
     case LBM_F64: return 8;
+    case LBM_F32X: return 4;
     default: return 0;
   }
 }
@@ -288,7 +289,7 @@ lbm_status lbm_restore(lbm_ctx* c, const void* src, int64_t t) {
 static lbm_status adj_check(lbm_ctx* c) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
-  if (c->p.storage != LBM_F32)
+  if (c->p.storage != LBM_F32 && c->p.storage != LBM_F32X)
     return fail(LBM_E_UNSUPPORTED, "the adjoint supports FP32 storage only");
   return LBM_OK;
 }

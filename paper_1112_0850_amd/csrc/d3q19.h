@@ -77,7 +77,7 @@ constexpr uint8_t FLAG_NOFORCE = 2;
 
 // Storage formats of the population offset g = f - w.  `load` widens a stored
 // element to the compute type, `store` rounds to nearest-even.
-enum StorageKind { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2, ST_F64 = 3 };
+enum StorageKind { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2, ST_F64 = 3, ST_F32X = 4 };
 
 template <int K>
 struct Storage;
@@ -88,6 +88,15 @@ struct Storage<ST_F32> {
   using C = float;
   __device__ static C load(T v, C) { return v; }
   __device__ static T store(C v, C) { return v; }
+};
+
+// FP32 storage with FP64 collision arithmetic (opt-in accuracy mode).
+template <>
+struct Storage<ST_F32X> {
+  using T = float;
+  using C = double;
+  __device__ static C load(T v, C) { return v; }
+  __device__ static T store(C v, C) { return T(v); }
 };
 
 template <>

@@ -779,6 +779,7 @@ hipError_t launch_init(int storage, const Geo& g, const PhysParams& ph, void* gr
     case ST_F16: init_t<ST_F16>(g, ph, grid, flags, rho0, u0, s); break;
     case ST_BF16: init_t<ST_BF16>(g, ph, grid, flags, rho0, u0, s); break;
     case ST_F64: init_t<ST_F64>(g, ph, grid, flags, rho0, u0, s); break;
+    case ST_F32X: init_t<ST_F32X>(g, ph, grid, flags, rho0, u0, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -797,6 +798,7 @@ hipError_t launch_mark_solids(int storage, const Geo& g, void* grid, const uint8
     case ST_F16: mark_t<ST_F16>(g, grid, flags, s); break;
     case ST_BF16: mark_t<ST_BF16>(g, grid, flags, s); break;
     case ST_F64: mark_t<ST_F64>(g, grid, flags, s); break;
+    case ST_F32X: mark_t<ST_F32X>(g, grid, flags, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -873,6 +875,7 @@ hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const
     case ST_F16: step_k<ST_F16>(solids, force, g, ph, src, dst, flags, s); break;
     case ST_BF16: step_k<ST_BF16>(solids, force, g, ph, src, dst, flags, s); break;
     case ST_F64: step_k<ST_F64>(solids, force, g, ph, src, dst, flags, s); break;
+    case ST_F32X: step_k<ST_F32X>(solids, force, g, ph, src, dst, flags, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -895,6 +898,7 @@ static hipError_t macro_o(int storage, const Geo& g, const PhysParams& ph, const
     case ST_F16: macro_t<ST_F16, O>(g, ph, grid, flags, rho, u, s); break;
     case ST_BF16: macro_t<ST_BF16, O>(g, ph, grid, flags, rho, u, s); break;
     case ST_F64: macro_t<ST_F64, O>(g, ph, grid, flags, rho, u, s); break;
+    case ST_F32X: macro_t<ST_F32X, O>(g, ph, grid, flags, rho, u, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -921,6 +925,7 @@ hipError_t launch_reduce(int storage, const Geo& g, const PhysParams& ph, const 
     case ST_F16: reduce_t<ST_F16>(g, ph, grid, flags, scratch, s); break;
     case ST_BF16: reduce_t<ST_BF16>(g, ph, grid, flags, scratch, s); break;
     case ST_F64: reduce_t<ST_F64>(g, ph, grid, flags, scratch, s); break;
+    case ST_F32X: reduce_t<ST_F32X>(g, ph, grid, flags, scratch, s); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();

@@ -12,9 +12,10 @@ import torch
 
 from . import _abi as A
 
-STORAGE = {"f32": A.LBM_F32, "f16": A.LBM_F16, "bf16": A.LBM_BF16, "f64": A.LBM_F64}
+STORAGE = {"f32": A.LBM_F32, "f16": A.LBM_F16, "bf16": A.LBM_BF16, "f64": A.LBM_F64,
+           "f32x": A.LBM_F32X}
 TORCH_DTYPE = {A.LBM_F32: torch.float32, A.LBM_F16: torch.float16,
-               A.LBM_BF16: torch.bfloat16, A.LBM_F64: torch.float64}
+               A.LBM_BF16: torch.bfloat16, A.LBM_F64: torch.float64, A.LBM_F32X: torch.float32}
 
 
 def _ptr(t):
@@ -40,7 +41,8 @@ def _as_field(x, shape, dtype, device, what):
 
 class LBM:
     """One D3Q19 BGK simulation on a periodic box (walls and obstacles are
-    solid flag bits).  ``storage`` in {'f32', 'f16', 'bf16', 'f64'}."""
+    solid flag bits).  ``storage`` in {'f32', 'f16', 'bf16', 'f64', 'f32x'}
+    ('f32x': FP32 storage with FP64 collision arithmetic)."""
 
     def __init__(self, shape, tau, force=(0.0, 0.0, 0.0), storage="f32", flags=None, u0=None,
                  rho0=None, f16_scale_log2=0, x_align=0, device="cuda"):

@@ -45,6 +45,7 @@ def test_byte_model_matches_paper():
     assert A.lbm_bytes_per_update(A.LBM_F64) == gold["bytes_per_update_gpu"]["dp"]
     assert A.lbm_bytes_per_update(A.LBM_F16) == 76
     assert A.lbm_bytes_per_update(A.LBM_BF16) == 76
+    assert A.lbm_bytes_per_update(A.LBM_F32X) == 152
     assert A.lbm_bytes_per_update(7) == 0
     # the CPU variant adds the write-allocate transfer: 3 transfers per PDF
     assert 19 * 3 * 4 == gold["bytes_per_update_cpu_write_allocate"]["sp"]

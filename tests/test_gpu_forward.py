@@ -17,14 +17,23 @@ from tests.gpu_util import check_solids, f_to_grid, grid_to_f, rel_linf, say
 
 pytestmark = pytest.mark.gpu
 
-STORAGES = ["f32", "f16", "bf16", "f64"]
+STORAGES = ["f32", "f16", "bf16", "f64", "f32x"]
+
+# FP32 *arithmetic* on a slowly evolving flow: every step rounds each
+# population at a few ulp of |g| ~ a omega |u| (a ~ 1/12), and in a flow that
+# is uniform along x and z those roundings are identical in every cell, so
+# they add up coherently over min(steps, H^2/(nu pi^2)) steps (2738 for the
+# 30-cell channel at tau = 0.6):  ~ 10 x 2^-24 x 0.14 x 2738 ~ 2.3e-4 relative
+# to |u|.  Cases of that kind are held to this bound in FP32 arithmetic and to
+# 1e-5 in the FP64-arithmetic mode (f32x) on the same FP32 storage.
+SLOW_FLOW_F32_TOL = 5e-4
 
 
 def _round_to(a, storage, s=0):
     """Round float64 offsets to what the storage type holds (values chosen so
     that every storage represents them exactly after this rounding)."""
     dt = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16,
-          "f64": torch.float64}[storage]
+          "f64": torch.float64, "f32x": torch.float32}[storage]
     return torch.from_numpy(a * 2.0 ** s).to(dt).to(torch.float64).numpy() / 2.0 ** s
 
 
@@ -111,7 +120,7 @@ def _macro_errors(sim, f, F, flags):
             float(np.abs(rho - rho_r)[fl].max() / np.abs(rho_r - 1)[fl].max()))
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f64", 1e-12)])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f64", 1e-12), ("f32x", 1e-6)])
 def test_taylor_green_parity(storage, tol):
     """Taylor-Green vortex, periodic 32^3, tau = 0.8, u0 = 0.01, 200 steps."""
     shape = (32, 32, 32)
@@ -136,18 +145,21 @@ def test_taylor_green_low_precision_error_stated(storage, tol):
     assert e_u <= tol
 
 
-def test_channel_parity():
-    """Channel 64x32x32 (walls at y = 0 and 31), tau = 0.6, g_x = 1e-6, FP32."""
+@pytest.mark.parametrize("storage,tol", [("f32", SLOW_FLOW_F32_TOL), ("f32x", 1e-5)])
+def test_channel_parity(storage, tol):
+    """Channel 64x32x32 (walls at y = 0 and 31), tau = 0.6, g_x = 1e-6,
+    5000 steps (the channel workload's step count on its oracle-sized copy)."""
     shape = (32, 32, 64)
-    say("channel parity f32", shape)
+    say("channel parity", storage, shape)
     flags = I.channel_flags(shape)
-    sim, f = _run_pair(shape, 0.6, (1e-6, 0, 0), "f32", flags, None, 500)
+    sim, f = _run_pair(shape, 0.6, (1e-6, 0, 0), storage, flags, None, 5000)
     e_rho, e_u, _ = _macro_errors(sim, f, (1e-6, 0, 0), flags)
     say(f"  rel L-inf rho {e_rho:.2e}  u {e_u:.2e}")
-    assert e_rho <= 1e-5 and e_u <= 1e-5
+    assert e_rho <= 1e-5 and e_u <= tol
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f64", 1e-12), ("f16", None), ("bf16", None)])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f64", 1e-12), ("f16", None), ("bf16", None),
+                                         ("f32x", 1e-6)])
 def test_porous_parity(storage, tol):
     """Porous periodic 64^3, 10% random spheres r in [4, 12], tau = 0.55,
     g_x = 1e-6, from a smooth random velocity, 100 steps."""
@@ -180,7 +192,7 @@ def test_ragged_shape_all_storages(storage):
     sim, f = _run_pair(shape, 0.65, F, storage, flags, u0, 40, s=8 if storage == "f16" else 0)
     e_rho, e_u, _ = _macro_errors(sim, f, F, flags)
     say(f"  rel L-inf rho {e_rho:.2e}  u {e_u:.2e}")
-    bound = {"f32": 1e-5, "f64": 1e-6, "f16": 1e-2, "bf16": 5e-2}[storage]
+    bound = {"f32": 1e-5, "f64": 1e-6, "f16": 1e-2, "bf16": 5e-2, "f32x": 1e-5}[storage]
     assert e_rho <= bound and e_u <= bound
     if storage == "f64":
         rho, u = sim.macroscopics(f64=True)
