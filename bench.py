@@ -248,10 +248,11 @@ def traffic_entry(alg_bytes, ms):
 
 
 KERNELS = {  # kernel-name prefix -> (storage, algorithmic bytes per fluid update)
-    "void lbm::k_step<0, true, true>": ("f32", 152),
-    "void lbm::k_step<1, true, true>": ("f16", 76),
-    "void lbm::k_step<2, true, true>": ("bf16", 76),
-    "void lbm::k_step<3, true, true>": ("f64", 304),
+    "void lbm::k_step<0, true, true, 1>": ("f32", 152),
+    "void lbm::k_step<1, true, true, 4>": ("f16", 76),
+    "void lbm::k_step<2, true, true, 4>": ("bf16", 76),
+    "void lbm::k_step<3, true, true, 1>": ("f64", 304),
+    "void lbm::k_step<4, true, true, 1>": ("f32x", 152),
 }
 
 
