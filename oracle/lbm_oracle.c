@@ -20,9 +20,18 @@
  *   - The stored state after n steps is the post-collision field f*(n).
  *     One step: stream f*(n) (with half-way bounce-back at solid neighbours),
  *     then collide every fluid cell.  f*(0) = f^eq(rho0, u0).
- *   - All axes are periodic.  flags: bit0 = solid, bit1 = no body force.
+ *   - All axes are periodic.  flags: bit0 = solid, bit1 = no body force,
+ *     bit2 = moving wall (a solid cell that moves with the velocity wall_u).
  *   - Body force: Guo, Zheng & Shi (Phys. Rev. E 65, 046308, 2002), with F
  *     a force density, applied on fluid cells without the no-force bit.
+ *   - Moving walls: the half-way bounce-back of a link into a moving solid
+ *     cell is corrected by the momentum the wall imparts (Ladd, J. Fluid
+ *     Mech. 271, 285, 1994), with the reference density rho0 = 1.
+ *   - Two equilibria (the `incompressible` argument): 0 = the second-order
+ *     LBGK equilibrium of Qian et al. with u = j/rho (the default); 1 = the
+ *     incompressible variant of He & Luo (J. Stat. Phys. 88, 927, 1997)
+ *     with u = j/rho0, rho0 = 1, which the paper's "incompressible flow
+ *     solver" (abstract, Sec. 2) may refer to.
  *
  * Every function names the passage of the paper (or the outside method) it
  * follows.  The paper defers the equilibrium to Qian et al. (1992); the
@@ -36,6 +45,7 @@
 #define Q 19
 #define FLAG_SOLID 1u
 #define FLAG_NOFORCE 2u
+#define FLAG_MOVING 4u
 
 /* ---------------------------------------------------------------------- */
 /* Lattice: Sec. 2 -- D3Q19, 19 discrete velocities in 3-D (Qian 1992).    */
@@ -115,13 +125,23 @@ static double cdot(int i, const double *v) {
 }
 
 /* Sec. 2 step 2: second-order LBGK equilibrium of Qian et al. (1992) with
- * c_s^2 = 1/3:  f^eq_i = w_i rho [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u]. */
-static void equilibrium(double rho, const double *u, double *feq) {
+ * c_s^2 = 1/3:  f^eq_i = w_i rho [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u].
+ * Incompressible variant (He & Luo 1997), rho0 = 1:
+ *               f^eq_i = w_i [rho + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u]. */
+static void equilibrium(double rho, const double *u, int incomp, double *feq) {
   double uu = dot3(u, u);
   for (int i = 0; i < Q; ++i) {
     double cu = cdot(i, u);
-    feq[i] = W[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
+    feq[i] = incomp ? W[i] * (rho + poly) : W[i] * rho * (1.0 + poly);
   }
+}
+
+/* The velocity of a cell from its moments: u = (j + F/2)/rho, or with the
+ * incompressible equilibrium u = (j + F/2)/rho0, rho0 = 1. */
+static void velocity(double rho, const double *j, const double *F, int incomp,
+                     double *u) {
+  for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * F[d]) / (incomp ? 1.0 : rho);
 }
 
 /* Guo et al. (2002) forcing term for BGK:
@@ -137,19 +157,19 @@ static void guo_source(double omega, const double *u, const double *F,
 }
 
 /* Sec. 2 steps 1-2 with Guo forcing: moments, equilibrium, relaxation.
- *   rho = sum f_i,  u = (sum f_i c_i + F/2) / rho,
+ *   rho = sum f_i,  u = (sum f_i c_i + F/2) / rho   (/ rho0 if incomp),
  *   f*_i = f_i - (1/tau) (f_i - f^eq_i) + S_i. */
-static void collide_cell(double omega, const double *F, const double *f,
-                         double *fout) {
+static void collide_cell(double omega, const double *F, int incomp,
+                         const double *f, double *fout) {
   double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < Q; ++i) {
     rho += f[i];
     for (int d = 0; d < 3; ++d) j[d] += f[i] * C[i][d];
   }
   double u[3];
-  for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * F[d]) / rho;
+  velocity(rho, j, F, incomp, u);
   double feq[Q], S[Q];
-  equilibrium(rho, u, feq);
+  equilibrium(rho, u, incomp, feq);
   guo_source(omega, u, F, S);
   for (int i = 0; i < Q; ++i) fout[i] = f[i] - omega * (f[i] - feq[i]) + S[i];
 }
@@ -157,34 +177,39 @@ static void collide_cell(double omega, const double *F, const double *f,
 /* Jacobians of the collision map of collide_cell, written out by the chain
  * rule (used by the discrete adjoint):
  *   J[i][j]  = d f*_i / d f_j,   JF[i][a] = d f*_i / d F_a.
- * d rho/d f_j = 1,  d u/d f_j = (c_j - u)/rho,  d u/d F = I/(2 rho). */
-static void collide_jacobian(double omega, const double *F, const double *f,
-                             double J[Q][Q], double JF[Q][3]) {
+ * d rho/d f_j = 1;  d u/d f_j = (c_j - u)/rho and d u/d F = I/(2 rho), or
+ * with the incompressible equilibrium d u/d f_j = c_j and d u/d F = I/2. */
+static void collide_jacobian(double omega, const double *F, int incomp,
+                             const double *f, double J[Q][Q], double JF[Q][3]) {
   double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
   for (int i = 0; i < Q; ++i) {
     rho += f[i];
     for (int d = 0; d < 3; ++d) j[d] += f[i] * C[i][d];
   }
   double u[3];
-  for (int d = 0; d < 3; ++d) u[d] = (j[d] + 0.5 * F[d]) / rho;
+  velocity(rho, j, F, incomp, u);
   double uu = dot3(u, u);
+  double rho_u = incomp ? 1.0 : rho; /* the density that divides j in u */
   for (int i = 0; i < Q; ++i) {
     double cu = cdot(i, u), cF = cdot(i, F);
-    double dfeq_drho = W[i] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;
+    double dfeq_drho = incomp ? W[i] : W[i] * (1.0 + poly);
     double dfeq_du[3], dS_du[3], dS_dF[3];
     for (int a = 0; a < 3; ++a) {
-      dfeq_du[a] = W[i] * rho * (3.0 * C[i][a] + 9.0 * cu * C[i][a] - 3.0 * u[a]);
+      dfeq_du[a] = W[i] * rho_u * (3.0 * C[i][a] + 9.0 * cu * C[i][a] - 3.0 * u[a]);
       dS_du[a] = (1.0 - 0.5 * omega) * W[i] * (-3.0 * F[a] + 9.0 * cF * C[i][a]);
       dS_dF[a] = (1.0 - 0.5 * omega) * W[i] * (3.0 * (C[i][a] - u[a]) + 9.0 * cu * C[i][a]);
     }
     for (int jj = 0; jj < Q; ++jj) {
       double v = ((i == jj) ? (1.0 - omega) : 0.0) + omega * dfeq_drho;
-      for (int a = 0; a < 3; ++a)
-        v += (omega * dfeq_du[a] + dS_du[a]) * (C[jj][a] - u[a]) / rho;
+      for (int a = 0; a < 3; ++a) {
+        double du_df = incomp ? C[jj][a] : (C[jj][a] - u[a]) / rho;
+        v += (omega * dfeq_du[a] + dS_du[a]) * du_df;
+      }
       J[i][jj] = v;
     }
     for (int a = 0; a < 3; ++a)
-      JF[i][a] = dS_dF[a] + (omega * dfeq_du[a] + dS_du[a]) / (2.0 * rho);
+      JF[i][a] = dS_dF[a] + (omega * dfeq_du[a] + dS_du[a]) / (2.0 * rho_u);
   }
 }
 
@@ -196,10 +221,10 @@ static void int_to_abi(const double *fi, double *fa) {
   for (int k = 0; k < Q; ++k) fa[k] = fi[ABI2INT[k]];
 }
 
-int oracle_equilibrium(double rho, const double *u, double *feq_abi) {
+int oracle_equilibrium(double rho, const double *u, int incomp, double *feq_abi) {
   if (lattice_init()) return -1;
   double t[Q];
-  equilibrium(rho, u, t);
+  equilibrium(rho, u, incomp, t);
   int_to_abi(t, feq_abi);
   return 0;
 }
@@ -213,23 +238,23 @@ int oracle_guo_source(double omega, const double *u, const double *F,
   return 0;
 }
 
-int oracle_collide(double tau, const double *F, const double *f_abi,
+int oracle_collide(double tau, const double *F, int incomp, const double *f_abi,
                    double *fstar_abi) {
   if (lattice_init()) return -1;
   double a[Q], b[Q];
   abi_to_int(f_abi, a);
-  collide_cell(1.0 / tau, F, a, b);
+  collide_cell(1.0 / tau, F, incomp, a, b);
   int_to_abi(b, fstar_abi);
   return 0;
 }
 
 /* J_abi[i][j] = d f*_i / d f_j, JF_abi[i][a] = d f*_i / d F_a (interface order). */
-int oracle_collide_jacobian(double tau, const double *F, const double *f_abi,
-                            double *J_abi, double *JF_abi) {
+int oracle_collide_jacobian(double tau, const double *F, int incomp,
+                            const double *f_abi, double *J_abi, double *JF_abi) {
   if (lattice_init()) return -1;
   double a[Q], J[Q][Q], JF[Q][3];
   abi_to_int(f_abi, a);
-  collide_jacobian(1.0 / tau, F, a, J, JF);
+  collide_jacobian(1.0 / tau, F, incomp, a, J, JF);
   for (int k = 0; k < Q; ++k) {
     for (int l = 0; l < Q; ++l) J_abi[k * Q + l] = J[ABI2INT[k]][ABI2INT[l]];
     for (int d = 0; d < 3; ++d) JF_abi[k * 3 + d] = JF[ABI2INT[k]][d];
@@ -251,6 +276,9 @@ static long cell(const grid *g, int x, int y, int z) {
 static int wrap(int v, int n) { return ((v % n) + n) % n; }
 static int is_solid(const uint8_t *flags, long c) {
   return flags && (flags[c] & FLAG_SOLID);
+}
+static int is_moving(const uint8_t *flags, long c) {
+  return flags && (flags[c] & FLAG_SOLID) && (flags[c] & FLAG_MOVING);
 }
 static void cell_force(const uint8_t *flags, long c, const double *F,
                        double *Fc) {
@@ -280,7 +308,7 @@ static int check_dims(int nx, int ny, int nz) {
 
 /* Initial state f*(0) = f^eq(rho0, u0) on fluid cells, 0 on solid cells.
  * rho0 may be NULL (uniform 1), u0 may be NULL (rest). */
-int oracle_init(int nx, int ny, int nz, const uint8_t *flags,
+int oracle_init(int nx, int ny, int nz, const uint8_t *flags, int incomp,
                 const double *rho0, const double *u0, double *f_abi) {
   if (lattice_init() || check_dims(nx, ny, nz)) return -1;
   grid g = {nx, ny, nz, (long)nx * ny * nz};
@@ -293,7 +321,7 @@ int oracle_init(int nx, int ny, int nz, const uint8_t *flags,
     double u[3] = {0.0, 0.0, 0.0};
     if (u0)
       for (int d = 0; d < 3; ++d) u[d] = u0[(long)d * g.n + c];
-    equilibrium(rho, u, a + c * Q);
+    equilibrium(rho, u, incomp, a + c * Q);
   }
   store_abi(&g, a, f_abi);
   free(a);
@@ -303,9 +331,12 @@ int oracle_init(int nx, int ny, int nz, const uint8_t *flags,
 /* Sec. 2 step 3 with the bounce-back of the obstacle paragraph: push the
  * post-collision values of every fluid cell to the neighbour along c_i; a
  * value that would enter a solid cell returns to its own cell reversed
- * (half-way bounce-back).  dst must be zeroed by the caller. */
-static void stream_push(const grid *g, const uint8_t *flags, const double *src,
-                        double *dst) {
+ * (half-way bounce-back).  If that solid cell is a moving wall, the returning
+ * value loses 2 w_i rho0 (c_i.u_w)/c_s^2 = 6 w_i (c_i.u_w) (Ladd 1994,
+ * rho0 = 1), so a wall moving along c_i sends less back against itself.
+ * wall_u may be NULL (no moving walls).  dst must be zeroed by the caller. */
+static void stream_push(const grid *g, const uint8_t *flags,
+                        const double *wall_u, const double *src, double *dst) {
 #pragma omp parallel for schedule(static)
   for (int z = 0; z < g->nz; ++z)
     for (int y = 0; y < g->ny; ++y)
@@ -317,6 +348,8 @@ static void stream_push(const grid *g, const uint8_t *flags, const double *src,
                         wrap(z + C[i][2], g->nz));
           if (!is_solid(flags, t))
             dst[t * Q + i] = src[c * Q + i];
+          else if (wall_u && is_moving(flags, t))
+            dst[c * Q + OPP[i]] = src[c * Q + i] - 6.0 * W[i] * cdot(i, wall_u);
           else
             dst[c * Q + OPP[i]] = src[c * Q + i];
         }
@@ -326,7 +359,8 @@ static void stream_push(const grid *g, const uint8_t *flags, const double *src,
 /* n full time steps of the two-lattice scheme (Sec. 2, last paragraph):
  * stream f*(t) into the second lattice, collide there, swap. */
 int oracle_step(int nx, int ny, int nz, double tau, const double *F,
-                const uint8_t *flags, double *f_abi, long nsteps) {
+                const uint8_t *flags, const double *wall_u, int incomp,
+                double *f_abi, long nsteps) {
   if (lattice_init() || check_dims(nx, ny, nz) || nsteps < 0) return -1;
   grid g = {nx, ny, nz, (long)nx * ny * nz};
   double omega = 1.0 / tau;
@@ -340,7 +374,7 @@ int oracle_step(int nx, int ny, int nz, double tau, const double *F,
   load_abi(&g, f_abi, a);
   for (long s = 0; s < nsteps; ++s) {
     memset(b, 0, (size_t)g.n * Q * sizeof(double));
-    stream_push(&g, flags, a, b);
+    stream_push(&g, flags, wall_u, a, b);
 #pragma omp parallel for schedule(static)
     for (long c = 0; c < g.n; ++c) {
       if (is_solid(flags, c)) {
@@ -349,7 +383,7 @@ int oracle_step(int nx, int ny, int nz, double tau, const double *F,
       }
       double Fc[3];
       cell_force(flags, c, F, Fc);
-      collide_cell(omega, Fc, b + c * Q, a + c * Q);
+      collide_cell(omega, Fc, incomp, b + c * Q, a + c * Q);
     }
   }
   store_abi(&g, a, f_abi);
@@ -359,8 +393,8 @@ int oracle_step(int nx, int ny, int nz, double tau, const double *F,
 }
 
 /* Pure streaming with bounce-back (no collision), for the tests. */
-int oracle_stream(int nx, int ny, int nz, const uint8_t *flags, double *f_abi,
-                  long nsteps) {
+int oracle_stream(int nx, int ny, int nz, const uint8_t *flags,
+                  const double *wall_u, double *f_abi, long nsteps) {
   if (lattice_init() || check_dims(nx, ny, nz) || nsteps < 0) return -1;
   grid g = {nx, ny, nz, (long)nx * ny * nz};
   double *a = malloc((size_t)g.n * Q * sizeof(double));
@@ -373,7 +407,7 @@ int oracle_stream(int nx, int ny, int nz, const uint8_t *flags, double *f_abi,
   load_abi(&g, f_abi, a);
   for (long s = 0; s < nsteps; ++s) {
     memset(b, 0, (size_t)g.n * Q * sizeof(double));
-    stream_push(&g, flags, a, b);
+    stream_push(&g, flags, wall_u, a, b);
     double *t = a;
     a = b;
     b = t;
@@ -385,11 +419,12 @@ int oracle_stream(int nx, int ny, int nz, const uint8_t *flags, double *f_abi,
 }
 
 /* Sec. 2 step 1, evaluated on the stored post-collision state:
- * rho = sum f*_i, rho u = sum f*_i c_i - F/2 (this equals the pre-collision
- * (rho, u) of the same step under Guo forcing).  Solid cells give 0. */
+ * rho = sum f*_i, rho u = sum f*_i c_i - F/2 (rho0 u with the incompressible
+ * equilibrium, rho0 = 1; either way this equals the pre-collision (rho, u) of
+ * the same step under Guo forcing).  Solid cells give 0. */
 int oracle_macroscopics(int nx, int ny, int nz, const double *F,
-                        const uint8_t *flags, const double *f_abi, double *rho,
-                        double *u) {
+                        const uint8_t *flags, int incomp, const double *f_abi,
+                        double *rho, double *u) {
   if (lattice_init() || check_dims(nx, ny, nz)) return -1;
   grid g = {nx, ny, nz, (long)nx * ny * nz};
 #pragma omp parallel for schedule(static)
@@ -407,15 +442,18 @@ int oracle_macroscopics(int nx, int ny, int nz, const double *F,
     if (rho) rho[c] = r;
     if (u)
       for (int d = 0; d < 3; ++d)
-        u[(long)d * g.n + c] = is_solid(flags, c) ? 0.0 : (m[d] - 0.5 * Fc[d]) / r;
+        u[(long)d * g.n + c] =
+            is_solid(flags, c) ? 0.0 : (m[d] - 0.5 * Fc[d]) / (incomp ? 1.0 : r);
   }
   return 0;
 }
 
 /* Global mass, momentum and kinetic energy over fluid cells:
- * out = {sum rho, sum rho u_x, sum rho u_y, sum rho u_z, sum rho |u|^2 / 2}. */
+ * out = {sum rho, sum rho u_x, sum rho u_y, sum rho u_z, sum rho |u|^2 / 2},
+ * with rho0 = 1 in place of rho in the last four for the incompressible
+ * equilibrium (its momentum density is rho0 u). */
 int oracle_reduce(int nx, int ny, int nz, const double *F, const uint8_t *flags,
-                  const double *f_abi, double *out5) {
+                  int incomp, const double *f_abi, double *out5) {
   if (lattice_init() || check_dims(nx, ny, nz)) return -1;
   grid g = {nx, ny, nz, (long)nx * ny * nz};
   double *rho = malloc((size_t)g.n * sizeof(double));
@@ -425,14 +463,15 @@ int oracle_reduce(int nx, int ny, int nz, const double *F, const uint8_t *flags,
     free(u);
     return -2;
   }
-  oracle_macroscopics(nx, ny, nz, F, flags, f_abi, rho, u);
+  oracle_macroscopics(nx, ny, nz, F, flags, incomp, f_abi, rho, u);
   double s[5] = {0, 0, 0, 0, 0};
   for (long c = 0; c < g.n; ++c) {
     if (is_solid(flags, c)) continue;
     double uc[3] = {u[c], u[g.n + c], u[2 * g.n + c]};
+    double m = incomp ? 1.0 : rho[c];
     s[0] += rho[c];
-    for (int d = 0; d < 3; ++d) s[1 + d] += rho[c] * uc[d];
-    s[4] += 0.5 * rho[c] * dot3(uc, uc);
+    for (int d = 0; d < 3; ++d) s[1 + d] += m * uc[d];
+    s[4] += 0.5 * m * dot3(uc, uc);
   }
   for (int k = 0; k < 5; ++k) out5[k] = s[k];
   free(rho);
@@ -447,9 +486,11 @@ int oracle_reduce(int nx, int ny, int nz, const double *F, const uint8_t *flags,
 
 /* Seed: lambda^T_i = dL/drho + dL/du . (c_i - u)/rho on fluid cells (0 on
  * solid), from rho = sum f*, u = (sum f* c - F/2)/rho;  dLdF += -dL/du/(2 rho)
- * on forced fluid cells (accumulated into dLdF[3]). */
+ * on forced fluid cells (accumulated into dLdF[3]).  With the incompressible
+ * equilibrium u = sum f* c - F/2, so lambda^T_i = dL/drho + dL/du . c_i and
+ * dLdF += -dL/du/2. */
 int oracle_adjoint_seed(int nx, int ny, int nz, const double *F,
-                        const uint8_t *flags, const double *fT_abi,
+                        const uint8_t *flags, int incomp, const double *fT_abi,
                         const double *dL_drho, const double *dL_du,
                         double *lam_abi, double *dLdF) {
   if (lattice_init() || check_dims(nx, ny, nz)) return -1;
@@ -461,7 +502,7 @@ int oracle_adjoint_seed(int nx, int ny, int nz, const double *F,
     free(u);
     return -2;
   }
-  oracle_macroscopics(nx, ny, nz, F, flags, fT_abi, rho, u);
+  oracle_macroscopics(nx, ny, nz, F, flags, incomp, fT_abi, rho, u);
   double acc[3] = {0, 0, 0};
   for (long c = 0; c < g.n; ++c) {
     if (is_solid(flags, c)) {
@@ -473,14 +514,16 @@ int oracle_adjoint_seed(int nx, int ny, int nz, const double *F,
     if (dL_du)
       for (int d = 0; d < 3; ++d) gu[d] = dL_du[(long)d * g.n + c];
     double uc[3] = {u[c], u[g.n + c], u[2 * g.n + c]};
+    double rho_u = incomp ? 1.0 : rho[c];
     for (int k = 0; k < Q; ++k) {
       double v = gr;
-      for (int d = 0; d < 3; ++d) v += gu[d] * (ABI_E[k][d] - uc[d]) / rho[c];
+      for (int d = 0; d < 3; ++d)
+        v += gu[d] * (incomp ? ABI_E[k][d] : (ABI_E[k][d] - uc[d]) / rho[c]);
       lam_abi[(long)k * g.n + c] = v;
     }
     int forced = !(flags && (flags[c] & FLAG_NOFORCE));
     if (forced)
-      for (int d = 0; d < 3; ++d) acc[d] += -gu[d] / (2.0 * rho[c]);
+      for (int d = 0; d < 3; ++d) acc[d] += -gu[d] / (2.0 * rho_u);
   }
   for (int d = 0; d < 3; ++d) dLdF[d] += acc[d];
   free(rho);
@@ -493,9 +536,11 @@ int oracle_adjoint_seed(int nx, int ny, int nz, const double *F,
  *   dLdF += JF(f(n+1))^T lambda^{n+1} at forced fluid cells;
  *   lambda^n = stream^T(mu): the transpose of the push-with-bounce-back is
  *   the gather  lambda^n_i(y) = mu_i(y + c_i) if that cell is fluid, else
- *   mu_{opp i}(y). */
+ *   mu_{opp i}(y).  The moving-wall correction is a constant of the
+ *   streaming, so it enters f(n+1) but not the transpose. */
 int oracle_adjoint_step(int nx, int ny, int nz, double tau, const double *F,
-                        const uint8_t *flags, const double *fn_abi,
+                        const uint8_t *flags, const double *wall_u, int incomp,
+                        const double *fn_abi,
                         const double *lam_np1_abi, double *lam_n_abi,
                         double *dLdF) {
   if (lattice_init() || check_dims(nx, ny, nz)) return -1;
@@ -516,13 +561,13 @@ int oracle_adjoint_step(int nx, int ny, int nz, double tau, const double *F,
   }
   load_abi(&g, fn_abi, a);
   load_abi(&g, lam_np1_abi, lam);
-  stream_push(&g, flags, a, b);
+  stream_push(&g, flags, wall_u, a, b);
 #pragma omp parallel for schedule(static)
   for (long c = 0; c < g.n; ++c) {
     if (is_solid(flags, c)) continue;
     double Fc[3], J[Q][Q], JF[Q][3];
     cell_force(flags, c, F, Fc);
-    collide_jacobian(omega, Fc, b + c * Q, J, JF);
+    collide_jacobian(omega, Fc, incomp, b + c * Q, J, JF);
     for (int jj = 0; jj < Q; ++jj) {
       double s = 0.0;
       for (int i = 0; i < Q; ++i) s += lam[c * Q + i] * J[i][jj];
@@ -565,9 +610,9 @@ int oracle_adjoint_step(int nx, int ny, int nz, double tau, const double *F,
 }
 
 /* Initial-state adjoint: f*(0)_i = f^eq_i(rho0, u0) on fluid cells, so
- *   dL/du0 = sum_i lambda^0_i d f^eq_i / d u,  dL/drho0 = sum_i lambda^0_i f^eq_i / rho0.
+ *   dL/du0 = sum_i lambda^0_i d f^eq_i / d u,  dL/drho0 = sum_i lambda^0_i d f^eq_i / d rho.
  * rho0 may be NULL (uniform 1); dL_drho0 may be NULL. */
-int oracle_adjoint_init(int nx, int ny, int nz, const uint8_t *flags,
+int oracle_adjoint_init(int nx, int ny, int nz, const uint8_t *flags, int incomp,
                         const double *rho0, const double *u0,
                         const double *lam0_abi, double *dL_du0,
                         double *dL_drho0) {
@@ -586,9 +631,10 @@ int oracle_adjoint_init(int nx, int ny, int nz, const uint8_t *flags,
         int i = ABI2INT[k];
         double lam = lam0_abi[(long)k * g.n + c];
         double cu = cdot(i, u);
-        gr += lam * W[i] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+        double rho_u = incomp ? 1.0 : rho;
+        gr += lam * (incomp ? W[i] : W[i] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
         for (int a = 0; a < 3; ++a)
-          gu[a] += lam * W[i] * rho * (3.0 * C[i][a] + 9.0 * cu * C[i][a] - 3.0 * u[a]);
+          gu[a] += lam * W[i] * rho_u * (3.0 * C[i][a] + 9.0 * cu * C[i][a] - 3.0 * u[a]);
       }
     }
     for (int a = 0; a < 3; ++a) dL_du0[(long)a * g.n + c] = gu[a];

@@ -18,6 +18,7 @@ import numpy as np
 
 FLAG_SOLID = 1
 FLAG_NOFORCE = 2
+FLAG_MOVING = 4
 
 _MASK64 = (1 << 64) - 1
 
@@ -62,6 +63,30 @@ def channel_flags(shape):
     f = np.zeros(shape, dtype=np.uint8)
     f[:, 0, :] = FLAG_SOLID
     f[:, ny - 1, :] = FLAG_SOLID
+    return f
+
+
+def couette_flags(shape):
+    """Plane Couette channel: a resting wall on the row y = 0 and a moving
+    wall (solid + moving bit) on the row y = ny - 1."""
+    nz, ny, nx = shape
+    f = np.zeros(shape, dtype=np.uint8)
+    f[:, 0, :] = FLAG_SOLID
+    f[:, ny - 1, :] = FLAG_SOLID | FLAG_MOVING
+    return f
+
+
+def cavity_flags(shape):
+    """Lid-driven cavity: a one-cell solid layer on all six faces of the box,
+    the whole top plane z = nz - 1 (edges included) being the moving lid."""
+    nz, ny, nx = shape
+    f = np.zeros(shape, dtype=np.uint8)
+    f[0, :, :] = FLAG_SOLID
+    f[:, 0, :] = FLAG_SOLID
+    f[:, ny - 1, :] = FLAG_SOLID
+    f[:, :, 0] = FLAG_SOLID
+    f[:, :, nx - 1] = FLAG_SOLID
+    f[nz - 1, :, :] = FLAG_SOLID | FLAG_MOVING
     return f
 
 

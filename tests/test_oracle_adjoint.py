@@ -10,25 +10,27 @@ from paper_1112_0850_amd import inputs as I
 from tests import lattice_ref as R
 
 
+@pytest.mark.parametrize("inc", [False, True])
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_collision_jacobian_vs_central_differences(seed):
+def test_collision_jacobian_vs_central_differences(seed, inc):
     _, w, _ = R.e_w_opp()
     rng = np.random.default_rng(seed)
     f = w * (1 + 0.1 * rng.standard_normal(19))
     tau = 0.55 + 0.5 * rng.random()
     F = 1e-2 * rng.standard_normal(3)
-    J, JF = O.collide_jacobian(tau, F, f)
+    J, JF = O.collide_jacobian(tau, F, f, incompressible=inc)
+    col = lambda F_, f_: O.collide(tau, F_, f_, incompressible=inc)
     h = 1e-6
     Jfd = np.zeros((19, 19))
     for j in range(19):
         d = np.zeros(19)
         d[j] = h
-        Jfd[:, j] = (O.collide(tau, F, f + d) - O.collide(tau, F, f - d)) / (2 * h)
+        Jfd[:, j] = (col(F, f + d) - col(F, f - d)) / (2 * h)
     JFfd = np.zeros((19, 3))
     for a in range(3):
         d = np.zeros(3)
         d[a] = h
-        JFfd[:, a] = (O.collide(tau, F + d, f) - O.collide(tau, F - d, f)) / (2 * h)
+        JFfd[:, a] = (col(F + d, f) - col(F - d, f)) / (2 * h)
     assert np.abs(J - Jfd).max() < 1e-9 * np.abs(J).max()
     assert np.abs(JF - JFfd).max() < 1e-9 * np.abs(JF).max()
 
@@ -54,46 +56,54 @@ def test_transposed_streaming_dot_product_exact():
     assert not PTy[:, flags == 1].any()
 
 
-def rollout_loss(u0, F, flags, tau, steps, target):
+def rollout_loss(u0, F, flags, tau, steps, target, wall_u=None, inc=False):
     """L = mean over fluid cells and components of (u_T - u*)^2."""
     shape = u0.shape[1:]
-    f = O.init(shape, flags, None, u0)
-    f = O.step(f, tau, F, flags, n=steps)
-    _, u = O.macroscopics(f, F, flags)
+    f = O.init(shape, flags, None, u0, incompressible=inc)
+    f = O.step(f, tau, F, flags, n=steps, wall_u=wall_u, incompressible=inc)
+    _, u = O.macroscopics(f, F, flags, incompressible=inc)
     fl = np.ones(shape, bool) if flags is None else (flags & 1) == 0
     return ((u - target) ** 2)[:, fl].mean()
 
 
-def rollout_grad(u0, F, flags, tau, steps, target):
+def rollout_grad(u0, F, flags, tau, steps, target, wall_u=None, inc=False):
     shape = u0.shape[1:]
     fl = np.ones(shape, bool) if flags is None else (flags & 1) == 0
-    states = [O.init(shape, flags, None, u0)]
+    states = [O.init(shape, flags, None, u0, incompressible=inc)]
     for _ in range(steps):
-        states.append(O.step(states[-1], tau, F, flags, n=1))
-    _, uT = O.macroscopics(states[-1], F, flags)
+        states.append(O.step(states[-1], tau, F, flags, n=1, wall_u=wall_u, incompressible=inc))
+    _, uT = O.macroscopics(states[-1], F, flags, incompressible=inc)
     gu = np.zeros_like(uT)
     gu[:, fl] = 2 * (uT - target)[:, fl] / (3 * fl.sum())
-    lam, dF = O.adjoint_seed(states[-1], None, gu, F, flags)
+    lam, dF = O.adjoint_seed(states[-1], None, gu, F, flags, incompressible=inc)
     for n in range(steps - 1, -1, -1):
-        lam, d = O.adjoint_step(states[n], lam, tau, F, flags)
+        lam, d = O.adjoint_step(states[n], lam, tau, F, flags, wall_u=wall_u, incompressible=inc)
         dF += d
-    du0, _ = O.adjoint_init(lam, u0, flags)
+    du0, _ = O.adjoint_init(lam, u0, flags, incompressible=inc)
     return du0, dF
 
 
-@pytest.mark.parametrize("solids", [False, True])
-def test_full_adjoint_vs_central_differences(solids):
+@pytest.mark.parametrize("solids,walls,inc", [(False, False, False), (True, False, False),
+                                              (True, True, False), (True, True, True),
+                                              (False, False, True)])
+def test_full_adjoint_vs_central_differences(solids, walls, inc):
+    """Variants: periodic; random solids with no-force cells; moving walls
+    (a lid-driven box whose lid moves along x, plus random solids) with the
+    Qian or the incompressible equilibrium; periodic incompressible."""
     n, tau, steps = 8, 0.6, 25
     shape = (n, n, n)
-    flags = None
+    flags, wall_u = None, None
     if solids:
         flags = I.random_flags(shape, 31, solid_fraction=0.15, noforce_fraction=0.2)
+    if walls:
+        flags = flags | I.cavity_flags(shape)
+        wall_u = (0.03, 0.0, 0.01)
     u0 = I.smooth_field(n, 2024, amplitude=0.02, modes=4)
     target = I.smooth_field(n, 7, amplitude=0.02, modes=4)
     F = np.array([1e-4, -5e-5, 2e-5])
     if flags is not None:
         u0[:, flags & 1 == 1] = 0
-    du0, dF = rollout_grad(u0, F, flags, tau, steps, target)
+    du0, dF = rollout_grad(u0, F, flags, tau, steps, target, wall_u, inc)
     # central differences at eps and eps/2, Richardson-extrapolated so the
     # O(eps^2) truncation cancels (the remaining error is O(eps^4)).
     def fd(fun, eps):
@@ -103,11 +113,13 @@ def test_full_adjoint_vs_central_differences(solids):
 
     for k, s in enumerate([101, 102]):
         v = I.smooth_field(n, s, amplitude=1.0, modes=4)
-        ref = fd(lambda e: rollout_loss(u0 + e * v, F, flags, tau, steps, target), 1e-4)
+        ref = fd(lambda e: rollout_loss(u0 + e * v, F, flags, tau, steps, target, wall_u, inc),
+                 1e-4)
         ad = (du0 * v).sum()
         assert abs(ad - ref) <= 1e-8 * abs(ref), (k, ad, ref)
     for a in range(3):
         d = np.zeros(3)
         d[a] = 1.0
-        ref = fd(lambda e: rollout_loss(u0, F + e * d, flags, tau, steps, target), 1e-5)
+        ref = fd(lambda e: rollout_loss(u0, F + e * d, flags, tau, steps, target, wall_u, inc),
+                 1e-5)
         assert abs(dF[a] - ref) <= 1e-8 * abs(ref), (a, dF[a], ref)

@@ -12,8 +12,10 @@ import pytest
 from oracle import oracle as O
 from tests import test_oracle_adjoint as TA
 from tests import test_oracle_dynamics as TD
+from tests import test_oracle_incompressible as TI
 from tests import test_oracle_lattice as TL
 from tests import test_oracle_streaming as TS
+from tests import test_oracle_walls as TW
 
 SRC = os.path.join(os.path.dirname(O.__file__), "lbm_oracle.c")
 
@@ -43,7 +45,7 @@ def _tgv():
 
 
 def _jac():
-    TA.test_collision_jacobian_vs_central_differences(0)
+    TA.test_collision_jacobian_vs_central_differences(0, False)
 
 
 def _dot():
@@ -51,43 +53,101 @@ def _dot():
 
 
 def _full_adj():
-    TA.test_full_adjoint_vs_central_differences(True)
+    TA.test_full_adjoint_vs_central_differences(True, False, False)
 
 
 def _conservation():
     TD.test_conservation(False)
 
 
+def _momentum():
+    TW.test_momentum_one_streaming_step((0.07, 0.0, 0.0))
+
+
+def _couette():
+    TW.test_couette_exact_steady_state(1.0, False)
+
+
+def _inc_eq():
+    TI.test_equilibrium_moments(1.03, (0.05, -0.02, 0.01))
+
+
+def _inc_collide():
+    TI.test_collision_conserves_and_relaxes()
+
+
+def _inc_read_back():
+    TI.test_macroscopics_read_back_the_initial_state()
+
+
+def _inc_jac():
+    TA.test_collision_jacobian_vs_central_differences(1, True)
+
+
+def _inc_full_adj():
+    TA.test_full_adjoint_vs_central_differences(False, False, True)
+
+
+def _walls_full_adj():
+    TA.test_full_adjoint_vs_central_differences(True, True, False)
+
+
 # (planted change: old text -> new text, first occurrence only; pins that must fail)
 MUTATIONS = {
-    "equilibrium_second_order": ("4.5 * cu * cu - 1.5 * uu);\n  }", "4.0 * cu * cu - 1.5 * uu);\n  }",
+    "equilibrium_second_order": ("double poly = 3.0 * cu + 4.5 * cu * cu", "double poly = 3.0 * cu + 4.0 * cu * cu",
                                  [_eq, _tgv]),
-    "equilibrium_uu_term": ("4.5 * cu * cu - 1.5 * uu);\n  }", "4.5 * cu * cu - 0.5 * uu);\n  }",
+    "equilibrium_uu_term": ("double poly = 3.0 * cu + 4.5 * cu * cu - 1.5 * uu;",
+                            "double poly = 3.0 * cu + 4.5 * cu * cu - 0.5 * uu;",
                             [_eq]),
     "guo_prefactor_sign": ("S[i] = (1.0 - 0.5 * omega)", "S[i] = (1.0 + 0.5 * omega)", [_guo]),
     "guo_dropped_u_term": ("(3.0 * (cF - uF) + 9.0 * cu * cF)", "(3.0 * cF + 9.0 * cu * cF)",
                            [_guo, _poiseuille]),
-    "half_force_in_velocity": ("u[d] = (j[d] + 0.5 * F[d]) / rho;\n  double feq",
-                               "u[d] = j[d] / rho;\n  double feq", [_poiseuille, _collide]),
+    "half_force_in_velocity": ("u[d] = (j[d] + 0.5 * F[d]) / (incomp", "u[d] = (j[d]) / (incomp",
+                               [_poiseuille, _collide]),
     "relaxation_sign": ("fout[i] = f[i] - omega * (f[i] - feq[i])",
                         "fout[i] = f[i] + omega * (f[i] - feq[i])", [_collide, _tgv]),
     "bounce_back_not_reversed": ("dst[c * Q + OPP[i]] = src[c * Q + i];",
                                  "dst[c * Q + i] = src[c * Q + i];", [_stream, _poiseuille]),
-    "macroscopic_force_shift": ("(m[d] - 0.5 * Fc[d]) / r", "(m[d] + 0.5 * Fc[d]) / r",
+    "macroscopic_force_shift": ("(m[d] - 0.5 * Fc[d]) / (incomp", "(m[d] + 0.5 * Fc[d]) / (incomp",
                                 [_poiseuille]),
     "weight_of_diagonals": ("(n2 == 1) ? 1.0 / 18.0 : 1.0 / 36.0", "(n2 == 1) ? 1.0 / 18.0 : 1.0 / 37.0",
                             [_eq, _conservation]),
-    "jacobian_velocity_derivative": ("* (C[jj][a] - u[a]) / rho;", "* (C[jj][a] + u[a]) / rho;",
+    "jacobian_velocity_derivative": (": (C[jj][a] - u[a]) / rho;", ": (C[jj][a] + u[a]) / rho;",
                                      [_jac]),
-    "jacobian_force_half": ("(omega * dfeq_du[a] + dS_du[a]) / (2.0 * rho);",
-                            "(omega * dfeq_du[a] + dS_du[a]) / rho;", [_jac]),
+    "jacobian_force_half": ("(omega * dfeq_du[a] + dS_du[a]) / (2.0 * rho_u);",
+                            "(omega * dfeq_du[a] + dS_du[a]) / rho_u;", [_jac]),
     "adjoint_transpose_index": ("mu[t * Q + i] : mu[c * Q + OPP[i]]", "mu[t * Q + i] : mu[c * Q + i]",
                                 [_dot]),
-    "adjoint_seed_force_sign": ("acc[d] += -gu[d] / (2.0 * rho[c]);", "acc[d] += gu[d] / (2.0 * rho[c]);",
+    "adjoint_seed_force_sign": ("acc[d] += -gu[d] / (2.0 * rho_u);", "acc[d] += gu[d] / (2.0 * rho_u);",
                                 [_full_adj]),
     "adjoint_init_dropped_term": ("9.0 * cu * C[i][a] - 3.0 * u[a]);\n      }\n    }\n    for (int a = 0; a < 3; ++a) dL_du0",
                                   "9.0 * cu * C[i][a]);\n      }\n    }\n    for (int a = 0; a < 3; ++a) dL_du0",
                                   [_full_adj]),
+    "moving_wall_sign": ("src[c * Q + i] - 6.0 * W[i] * cdot(i, wall_u)",
+                         "src[c * Q + i] + 6.0 * W[i] * cdot(i, wall_u)", [_momentum, _couette]),
+    "moving_wall_factor": ("src[c * Q + i] - 6.0 * W[i] * cdot(i, wall_u)",
+                           "src[c * Q + i] - 3.0 * W[i] * cdot(i, wall_u)", [_momentum, _couette]),
+    "moving_wall_direction": ("src[c * Q + i] - 6.0 * W[i] * cdot(i, wall_u)",
+                              "src[c * Q + i] - 6.0 * W[i] * cdot(OPP[i], wall_u)",
+                              [_momentum, _couette]),
+    "moving_bit_ignored": ("else if (wall_u && is_moving(flags, t))",
+                           "else if (wall_u && 0 && is_moving(flags, t))",
+                           [_momentum, _couette]),
+    "adjoint_recompute_without_walls": ("stream_push(&g, flags, wall_u, a, b);\n#pragma omp parallel for schedule(static)\n  for (long c = 0; c < g.n; ++c) {\n    if (is_solid(flags, c)) continue;\n    double Fc[3], J",
+                                        "stream_push(&g, flags, NULL, a, b);\n#pragma omp parallel for schedule(static)\n  for (long c = 0; c < g.n; ++c) {\n    if (is_solid(flags, c)) continue;\n    double Fc[3], J",
+                                        [_walls_full_adj]),
+    "incompressible_equilibrium_rho": ("incomp ? W[i] * (rho + poly)", "incomp ? W[i] * rho * (1.0 + poly)",
+                                       [_inc_eq]),
+    "incompressible_velocity": ("(j[d] + 0.5 * F[d]) / (incomp ? 1.0 : rho)", "(j[d] + 0.5 * F[d]) / rho",
+                                [_inc_collide]),
+    "incompressible_macroscopics": ("(m[d] - 0.5 * Fc[d]) / (incomp ? 1.0 : r)",
+                                    "(m[d] - 0.5 * Fc[d]) / r", [_inc_read_back]),
+    "incompressible_jacobian_du": ("double du_df = incomp ? C[jj][a] :",
+                                   "double du_df = incomp ? (C[jj][a] - u[a]) :", [_inc_jac]),
+    "incompressible_jacobian_drho": ("double dfeq_drho = incomp ? W[i] :",
+                                     "double dfeq_drho = incomp ? W[i] * (1.0 + poly) :", [_inc_jac]),
+    "incompressible_seed": ("v += gu[d] * (incomp ? ABI_E[k][d] :",
+                            "v += gu[d] * (incomp ? ABI_E[k][d] - uc[d] :", [_inc_full_adj]),
 }
 
 

@@ -1,0 +1,107 @@
+"""Pins of the oracle's moving-wall bounce-back (no GPU).  The half-way
+bounce-back of a link into a wall moving with u_w carries the momentum the
+wall imparts (Ladd 1994, reference density 1): closed forms for the momentum
+one streaming step transfers, plane Couette flow (whose steady state the
+scheme reproduces exactly: a linear profile has no second derivative for the
+bounce-back slip error to act on), a zero wall velocity reducing to the plain
+bounce-back of the obstacle paragraph (Sec. 2), and the mirror symmetry and
+mass conservation of the lid-driven cavity (Sec. 6)."""
+from fractions import Fraction
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1112_0850_amd import inputs as I
+from tests import lattice_ref as R
+
+
+def test_zero_wall_velocity_is_plain_bounce_back():
+    shape = (6, 7, 5)
+    flags = I.random_flags(shape, 41, solid_fraction=0.25, noforce_fraction=0.1)
+    moving = flags | np.where(flags & 1, I.FLAG_MOVING, 0).astype(np.uint8)
+    u0 = 0.05 * I.random_offsets(shape, 3)[:3] / 1e-2
+    f0 = O.init(shape, flags, None, u0)
+    ref = O.step(f0, 0.7, (1e-4, 0, 0), flags, n=10)
+    a = O.step(f0, 0.7, (1e-4, 0, 0), moving, n=10, wall_u=(0.0, 0.0, 0.0))
+    b = O.step(f0, 0.7, (1e-4, 0, 0), moving, n=10, wall_u=None)
+    assert np.array_equal(a, ref) and np.array_equal(b, ref)
+    # and the moving bit on its own (no solid bit) marks nothing
+    stray = flags | np.where(flags & 1, 0, I.FLAG_MOVING).astype(np.uint8)
+    c = O.step(f0, 0.7, (1e-4, 0, 0), stray, n=10, wall_u=(0.1, 0.0, 0.0))
+    assert np.array_equal(c, ref)
+
+
+@pytest.mark.parametrize("uw", [(0.07, 0.0, 0.0), (0.0, 0.0, -0.03), (0.05, 0.02, -0.01)])
+def test_momentum_one_streaming_step(uw):
+    """Fluid at rest (f = w) beside a wall moving with u_w, one pure
+    streaming step: every link leaving the wall cell into the fluid gains
+    6 w_j (c_j.u_w), so each fluid cell under the wall gains mass
+    6 sum_j w_j (c_j.u_w) and momentum 6 sum_j w_j (c_j.u_w) c_j, the sums
+    over the five directions with c_y = -1 (exact rationals).  For a wall
+    velocity along the wall this is (u_x/3, 0, u_z/3) and no mass."""
+    nz, ny, nx = 3, 6, 5
+    shape = (nz, ny, nx)
+    fl = I.couette_flags(shape)  # moving wall on the row y = ny - 1
+    e, w, _ = R.e_w_opp()
+    f0 = O.init(shape, fl)
+    f1 = O.stream(f0, fl, n=1, wall_u=uw)
+    ex = [Fraction(v).limit_denominator(10 ** 6) for v in uw]
+    dm = Fraction(0)
+    dp = [Fraction(0)] * 3
+    for c, wt in zip(R.INTERFACE_ORDER, (R.WEIGHT_BY_NORM2[sum(x * x for x in c)]
+                                         for c in R.INTERFACE_ORDER)):
+        if c[1] != -1:
+            continue
+        k = 6 * wt * sum(ci * ui for ci, ui in zip(c, ex))
+        dm += k
+        dp = [p + k * ci for p, ci in zip(dp, c)]
+    cells = nx * nz
+    P = np.einsum("ia,izyx->a", e.astype(np.float64), f1)
+    assert abs((f1.sum() - f0.sum()) - cells * float(dm)) < 1e-14
+    assert np.abs(P - cells * np.array([float(v) for v in dp])).max() < 1e-14
+    if uw[1] == 0.0:
+        assert dm == 0
+        assert np.abs(P - cells * np.array([uw[0] / 3, 0.0, uw[2] / 3])).max() < 1e-14
+
+
+@pytest.mark.parametrize("incompressible", [False, True])
+@pytest.mark.parametrize("tau", [0.6, 1.0])
+def test_couette_exact_steady_state(tau, incompressible):
+    """Resting wall at y = 0, wall moving with (U, 0, 0) at y = ny - 1; the
+    half-way walls sit at y = 1/2 and y = ny - 3/2, so the steady profile is
+    u_x = U (y - 1/2)/H, H = ny - 2, with rho = 1 and u_y = u_z = 0."""
+    ny, U = 18, 0.05
+    shape = (1, ny, 1)
+    fl = I.couette_flags(shape)
+    nu = (tau - 0.5) / 3
+    H = ny - 2
+    steps = int(30 * H * H / (nu * math.pi ** 2))
+    f = O.step(O.init(shape, fl, incompressible=incompressible), tau, (0, 0, 0), fl, n=steps,
+               wall_u=(U, 0, 0), incompressible=incompressible)
+    rho, u = O.macroscopics(f, (0, 0, 0), fl, incompressible=incompressible)
+    y = np.arange(1, ny - 1)
+    assert np.abs(u[0, 0, 1:-1, 0] - U * (y - 0.5) / H).max() <= 1e-10 * U
+    assert np.abs(u[1:, 0, 1:-1, 0]).max() <= 1e-12 * U
+    assert np.abs(rho[0, 1:-1, 0] - 1).max() < 1e-10
+
+
+def test_cavity_mass_and_mirror_symmetry():
+    """Lid-driven cavity, lid moving along x: mass is conserved exactly (the
+    lid covers the whole top plane, so every fluid cell under it receives
+    corrections that sum to zero), and the flow is mirror-symmetric about the
+    mid-plane of y: u_x, u_z even and u_y odd."""
+    shape = (10, 9, 11)
+    fl = I.cavity_flags(shape)
+    f0 = O.init(shape, fl)
+    f = O.step(f0, 0.6, (0, 0, 0), fl, n=150, wall_u=(0.08, 0, 0))
+    r0, r1 = O.reduce(f0, (0, 0, 0), fl), O.reduce(f, (0, 0, 0), fl)
+    assert abs(r1[0] - r0[0]) <= 1e-13 * r0[0]
+    rho, u = O.macroscopics(f, (0, 0, 0), fl)
+    m = u[:, :, ::-1, :]
+    assert np.abs(u[0]).max() > 1e-3
+    assert np.abs(u[0] - m[0]).max() < 1e-14
+    assert np.abs(u[1] + m[1]).max() < 1e-14
+    assert np.abs(u[2] - m[2]).max() < 1e-14
+    assert np.abs(rho - rho[:, ::-1, :]).max() < 1e-14
