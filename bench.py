@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic porous box")
     ap.add_argument("--only", default="",
-                    help="comma list of legs: f32,f16,bf16,f64,f32x,adjoint,copy,cpu,large")
+                    help="comma list of legs: f32,f16,bf16,f64,f32x,adjoint,copy,cpu,large,cavity")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--sweep", action="store_true",
                     help="domain-size sweep instead of the headline run: periodic all-fluid cubes "
@@ -106,6 +106,32 @@ def large_leg(torch, storage, n, steps=100, warmup=5):
            "ms_per_step": ms, "mlups": n_cells / ms / 1e3, "mflups": n_fluid / ms / 1e3,
            "alg_gbs": alg / ms / 1e6, "hbm_frac": alg / ms / 1e6 / HBM_PEAK_GBS,
            "mass_drift_rel": abs(m1 - m0) / m0, "steps": steps + warmup}
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def cavity_leg(torch, storage, n, steps, warmup, s=0):
+    """Lid-driven cavity (the paper's verification workload, Sec. 6): n^3 box
+    with a one-cell solid layer on all faces, the top plane moving with
+    (0.05, 0, 0), tau 0.55, from rest -- the moving-wall step kernel."""
+    from paper_1112_0850_amd import _abi as A
+    from paper_1112_0850_amd import inputs as I
+    from paper_1112_0850_amd.lbm import LBM
+    flags = I.cavity_flags((n, n, n))
+    sim = LBM((n, n, n), 0.55, (0.0, 0.0, 0.0), storage, flags=torch.from_numpy(flags).cuda(),
+              wall_u=(0.05, 0.0, 0.0), f16_scale_log2=s)
+    m0 = float(sim.reduce()[0].item())
+    ms = timed_steps(sim, torch, steps, warmup)
+    m1 = float(sim.reduce()[0].item())
+    n_fluid = (n - 2) ** 3
+    alg = A.lbm_bytes_per_update(sim.storage) * n_fluid + n ** 3
+    out = {"workload": f"{n}^3 lid-driven cavity, lid (0.05, 0, 0), tau 0.55, {storage}",
+           "ms_per_step": ms, "mlups": n ** 3 / ms / 1e3, "mflups": n_fluid / ms / 1e3,
+           "alg_gbs": alg / ms / 1e6, "hbm_frac": alg / ms / 1e6 / HBM_PEAK_GBS,
+           "mass_drift_rel": abs(m1 - m0) / m0}
+    if storage == "f16":
+        out["f16_scale_log2"] = s
     del sim
     torch.cuda.empty_cache()
     return out
@@ -257,11 +283,11 @@ def traffic_entry(alg_bytes, ms):
 
 
 KERNELS = {  # kernel-name prefix -> (storage, algorithmic bytes per fluid update)
-    "void lbm::k_step<0, true, true, 1>": ("f32", 152),
-    "void lbm::k_step<1, true, true, 4>": ("f16", 76),
-    "void lbm::k_step<2, true, true, 4>": ("bf16", 76),
-    "void lbm::k_step<3, true, true, 1>": ("f64", 304),
-    "void lbm::k_step<4, true, true, 1>": ("f32x", 152),
+    "void lbm::k_step<0, 1, true, false, 1>": ("f32", 152),
+    "void lbm::k_step<1, 1, true, false, 4>": ("f16", 76),
+    "void lbm::k_step<2, 1, true, false, 4>": ("bf16", 76),
+    "void lbm::k_step<3, 1, true, false, 1>": ("f64", 304),
+    "void lbm::k_step<4, 1, true, false, 1>": ("f32x", 152),
 }
 
 
@@ -347,7 +373,7 @@ def main():
         return sweep(torch)
 
     legs = set(args.only.split(",")) if args.only else {"f32", "f16", "bf16", "f64", "f32x",
-                                                        "adjoint", "copy", "cpu", "large"}
+                                                        "adjoint", "copy", "cpu", "large", "cavity"}
     n = args.n
     log(f"geometry: {n}^3 sphere pack, 10% solid, seed 12345")
     flags = I.sphere_pack((n, n, n), 0.10, seed=12345)
@@ -364,6 +390,11 @@ def main():
             res[st] = forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st, args.steps,
                                   args.warmup, s)
             log(f"  {res[st]['mlups']:.0f} MLUPS, {res[st]['alg_gbs']:.0f} GB/s algorithmic")
+    if "cavity" in legs:
+        log(f"lid-driven cavity {n}^3, f32 and f16")
+        res["cavity"] = [cavity_leg(torch, "f32", n, args.steps, args.warmup),
+                         cavity_leg(torch, "f16", n, args.steps, args.warmup, 10)]
+        log("  " + ", ".join(f"{c['mlups']:.0f}" for c in res["cavity"]) + " MLUPS")
     if "adjoint" in legs:
         log("adjoint 128^3")
         res["adjoint"] = adjoint_leg(torch)
@@ -399,7 +430,7 @@ def main():
             "bound": "hbm", "achieved": main_leg["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": main_leg["hbm_frac"],
             "traffic": traffic_entry(main_leg["alg_bytes_per_step"], main_leg["ms_per_step"]),
-            "kernel": "k_step<F32, solids, force>",
+            "kernel": "k_step<F32, static walls, force, Qian>",
             "alg_bytes_per_launch": main_leg["alg_bytes_per_step"],
         }
     if "cpu" in res:
@@ -414,6 +445,8 @@ def main():
         line["adjoint"] = res["adjoint"]
     if "large" in res:
         line["large"] = res["large"]
+    if "cavity" in res:
+        line["cavity"] = res["cavity"]
     if "copy" in res:
         line["copy_gbs"] = res["copy"]["gbs"]
         if main_leg:

@@ -6,7 +6,13 @@
  * D3Q19 lattice with the equilibrium of Qian et al. (1992), updated with the
  * fused stream-collide ("pull") ordering and two lattices of Sec. 6; obstacle
  * cells handled by bounce-back (Sec. 2, last paragraph) in its half-way form;
- * body force by Guo, Zheng & Shi (Phys. Rev. E 65, 046308, 2002).
+ * body force by Guo, Zheng & Shi (Phys. Rev. E 65, 046308, 2002).  Options:
+ * walls moving with one common velocity (the lid of the lid-driven cavity
+ * the paper verifies on, Sec. 6), by Ladd's momentum-corrected bounce-back
+ * (J. Fluid Mech. 271, 285, 1994) with reference density 1; and the
+ * incompressible equilibrium of He & Luo (J. Stat. Phys. 88, 927, 1997) in
+ * place of Qian's (the paper's "incompressible flow solver", abstract and
+ * Sec. 2).
  *
  * Conventions shared by every call
  * --------------------------------
@@ -29,22 +35,29 @@
  *    Every store rounds to nearest-even.  Collision arithmetic is FP32 for
  *    F32/F16/BF16 storage and FP64 for F64 and F32X storage.
  *    Solid cells carry no state of their own: every slot of a solid cell
- *    holds a quiet-NaN marker (rewritten each step by the cell's own
- *    thread).  A pull that reads the marker takes the half-way bounce-back
- *    value from the pulling cell's own opposite slot instead.  Padding
- *    stays 0.  The library maintains the markers itself (init, step,
+ *    holds a marker (rewritten each step by the cell's own thread): a quiet
+ *    NaN, or +infinity for a moving-wall cell when the wall velocity is not
+ *    zero.  A pull that reads a marker takes the half-way bounce-back value
+ *    from the pulling cell's own opposite slot instead, plus the moving-wall
+ *    term 6 w_i (c_i . u_w) in storage units for an infinity marker.
+ *    Padding stays 0.  The library maintains the markers itself (init, step,
  *    save/restore); after writing a grid from outside, call
- *    lbm_refresh_solids.  Fluid values must never be NaN.
+ *    lbm_refresh_solids.  Fluid values must never be NaN (nor infinite
+ *    when the wall velocity is not zero).
  *  - Scalar fields are [nz][ny][nx], vector fields [3][nz][ny][nx] (no
  *    padding).  flags are uint8 [nz][ny][nx]: bit0 LBM_FLAG_SOLID (obstacle
  *    cell, never read or written), bit1 LBM_FLAG_NOFORCE (fluid cell without
- *    body force); other bits are reserved and ignored.  flags == NULL means
- *    all fluid.
+ *    body force), bit2 LBM_FLAG_MOVING (with bit0: a wall cell moving with
+ *    lbm_params.wall_u; ignored without bit0); other bits are reserved and
+ *    ignored.  flags == NULL means all fluid.
  *  - All axes are periodic; walls are rows of solid cells.
  *  - Time levels: after lbm_init the current grid holds f*(0) = f^eq(rho0,u0)
  *    (solid cells 0); each step streams with half-way bounce-back and then
  *    collides:  f*_i(x, t+1) = Omega_i( f_i(x, t+1) ),
- *      f_i(x, t+1) = f*_i(x - c_i, t)  if x - c_i is fluid, else f*_{opp i}(x, t).
+ *      f_i(x, t+1) = f*_i(x - c_i, t)  if x - c_i is fluid, else f*_{opp i}(x, t)
+ *                    (+ 6 w_i (c_i . u_w) if x - c_i is a moving wall).
+ *  - Velocity: u = (j + F/2)/rho with Qian's equilibrium, u = j + F/2 with
+ *    the incompressible one (rho0 = 1), j = sum f_i c_i.
  *  - Every pointer is device memory owned by the caller, 256-byte aligned,
  *    and must stay valid while work that uses it is queued.  Calls enqueue
  *    on the context's stream and return without synchronising; nothing in
@@ -85,7 +98,12 @@ typedef enum {
                    converging runs, where FP32 arithmetic errors accumulate */
 } lbm_storage;
 
-enum { LBM_FLAG_SOLID = 1, LBM_FLAG_NOFORCE = 2 };
+typedef enum {
+  LBM_EQ_QIAN = 0,           /* f^eq_i = w_i rho [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u] */
+  LBM_EQ_INCOMPRESSIBLE = 1  /* f^eq_i = w_i [rho + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u] */
+} lbm_equilibrium;
+
+enum { LBM_FLAG_SOLID = 1, LBM_FLAG_NOFORCE = 2, LBM_FLAG_MOVING = 4 };
 
 typedef struct {
   int32_t nx, ny, nz;     /* cells per axis, each >= 1 */
@@ -96,6 +114,11 @@ typedef struct {
   double tau;             /* BGK relaxation time, > 1/2, or +INFINITY
                              (omega = 0: pure streaming, a test mode) */
   double force[3];        /* Guo body-force density, finite */
+  double wall_u[3];       /* velocity of the cells flagged SOLID | MOVING,
+                             finite (tangential to the wall for a physical
+                             moving wall); all 0 = every wall at rest */
+  int32_t equilibrium;    /* lbm_equilibrium */
+  int32_t reserved;       /* must be 0 */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -151,14 +174,17 @@ lbm_status lbm_step_from(lbm_ctx* ctx, const void* src, void* dst);
 
 /* Macroscopic fields of the current time level t from the stored f*(t):
  * rho = sum f*_i, rho u = sum f*_i c_i - F/2 (equal to the pre-collision
- * moments of step t under Guo forcing; F = 0 on no-force cells).  Solid
+ * moments of step t under Guo forcing; F = 0 on no-force cells; rho0 u with
+ * rho0 = 1 for the incompressible equilibrium).  Solid
  * cells get rho = 0, u = 0.  Either output may be NULL.  The _f64 variant
  * computes and writes in FP64.  Errors: LBM_E_ARG, LBM_E_HIP. */
 lbm_status lbm_macroscopics(lbm_ctx* ctx, float* rho, float* u);
 lbm_status lbm_macroscopics_f64(lbm_ctx* ctx, double* rho, double* u);
 
 /* Global FP64 sums over fluid cells of the current time level:
- * out5 = {sum rho, sum rho u_x, sum rho u_y, sum rho u_z, sum rho |u|^2 / 2},
+ * out5 = {sum rho, sum rho u_x, sum rho u_y, sum rho u_z, sum rho |u|^2 / 2}
+ * (rho0 = 1 in place of rho in the last four for the incompressible
+ * equilibrium),
  * written to DEVICE memory out5 (5 doubles).  Deterministic (fixed-order
  * two-pass tree reduction, no atomics); uses the context's scratch.
  * Errors: LBM_E_ARG, LBM_E_HIP. */
@@ -183,20 +209,25 @@ lbm_status lbm_refresh_solids(lbm_ctx* ctx);
 lbm_status lbm_save(lbm_ctx* ctx, void* dst);
 lbm_status lbm_restore(lbm_ctx* ctx, const void* src, int64_t t);
 
-/* ---- discrete adjoint (LBM_F32 storage only) ------------------------------
+/* ---- discrete adjoint (LBM_F32 / LBM_F32X storage) ------------------------
  * Reverse mode of the update above for an objective L of the final
- * macroscopic fields (FP32 or FP32X storage; FP32 adjoint arithmetic).  lambda^n = dL/d f*(n) is FP32 in the grid layout
+ * macroscopic fields (FP32 adjoint arithmetic), with either equilibrium and
+ * with moving walls (the wall velocity is a constant of the map, so it
+ * enters the recomputed state but not the transpose; no gradient is formed
+ * for it).  lambda^n = dL/d f*(n) is FP32 in the grid layout
  * ([19][nz][ny][x_stride] floats); its solid-cell and padding slots must be
  * zero when first used (the seed writes zeros there and the step never
  * writes them).  dL/dF is accumulated per thread block in an FP64 partials
  * buffer (adj_partials_bytes) without atomics; lbm_adjoint_finish_dF reduces
- * it in a fixed order.  Errors: LBM_E_UNSUPPORTED for non-F32 storage,
+ * it in a fixed order.  Errors: LBM_E_UNSUPPORTED for other storage types,
  * LBM_E_ARG, LBM_E_HIP. */
 
 /* Seed from dL/drho_T (float [nz][ny][nx] or NULL = 0) and dL/du_T (float
  * [3][nz][ny][nx] or NULL = 0) at the current time level:
- *   lambda^T_i = dL/drho + dL/du . (c_i - u)/rho;
- * (re)initialises the partials with the term -dL/du / (2 rho). */
+ *   lambda^T_i = dL/drho + dL/du . (c_i - u)/rho
+ * (dL/drho + dL/du . c_i for the incompressible equilibrium);
+ * (re)initialises the partials with the term -dL/du / (2 rho) (rho -> 1 for
+ * the incompressible equilibrium). */
 lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const float* dL_drho, const float* dL_du,
                             float* lam_T, double* dLdF_partials);
 

@@ -12,7 +12,8 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_E_ARG, LBM_E_HIP, LBM_E_UNSUPPORTED, LBM_E_STATE = 0, -1, -2, -3, -4
 LBM_F32, LBM_F16, LBM_BF16, LBM_F64, LBM_F32X = 0, 1, 2, 3, 4
-LBM_FLAG_SOLID, LBM_FLAG_NOFORCE = 1, 2
+LBM_FLAG_SOLID, LBM_FLAG_NOFORCE, LBM_FLAG_MOVING = 1, 2, 4
+LBM_EQ_QIAN, LBM_EQ_INCOMPRESSIBLE = 0, 1
 
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_HIP", -3: "LBM_E_UNSUPPORTED",
                 -4: "LBM_E_STATE"}
@@ -21,7 +22,8 @@ STATUS_NAMES = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_HIP", -3: "LBM_E_UNSUPP
 class lbm_params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("storage", C.c_int32), ("f16_scale_log2", C.c_int32), ("x_align", C.c_int32),
-                ("tau", C.c_double), ("force", C.c_double * 3)]
+                ("tau", C.c_double), ("force", C.c_double * 3), ("wall_u", C.c_double * 3),
+                ("equilibrium", C.c_int32), ("reserved", C.c_int32)]
 
 
 class LBMError(RuntimeError):
@@ -85,7 +87,8 @@ def check(status):
     return status
 
 
-def params(shape, tau, force=(0.0, 0.0, 0.0), storage=LBM_F32, f16_scale_log2=0, x_align=0):
+def params(shape, tau, force=(0.0, 0.0, 0.0), storage=LBM_F32, f16_scale_log2=0, x_align=0,
+           wall_u=(0.0, 0.0, 0.0), equilibrium=LBM_EQ_QIAN):
     nz, ny, nx = shape
     p = lbm_params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -95,6 +98,9 @@ def params(shape, tau, force=(0.0, 0.0, 0.0), storage=LBM_F32, f16_scale_log2=0,
     p.tau = float(tau)
     for d in range(3):
         p.force[d] = float(force[d])
+        p.wall_u[d] = float(wall_u[d])
+    p.equilibrium = int(equilibrium)
+    p.reserved = 0
     return p
 
 

@@ -61,6 +61,11 @@ lbm_status check_params(const lbm_params* p, Sizes* sz) {
     return fail(LBM_E_ARG, "tau must be > 1/2 or +infinity (got %g)", p->tau);
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(p->force[d])) return fail(LBM_E_ARG, "force[%d] is not finite", d);
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(p->wall_u[d])) return fail(LBM_E_ARG, "wall_u[%d] is not finite", d);
+  if (p->equilibrium != LBM_EQ_QIAN && p->equilibrium != LBM_EQ_INCOMPRESSIBLE)
+    return fail(LBM_E_ARG, "unknown equilibrium %d", p->equilibrium);
+  if (p->reserved != 0) return fail(LBM_E_ARG, "reserved must be 0");
   if (p->storage == LBM_F16 && (p->f16_scale_log2 < -24 || p->f16_scale_log2 > 24))
     return fail(LBM_E_ARG, "f16_scale_log2 must be in [-24, 24] (got %d)", p->f16_scale_log2);
   if (p->x_align < 0 || p->x_align > 4096)
@@ -170,6 +175,10 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* grid_a, void* grid
   c->ph.omega = std::isinf(p->tau) ? 0.0 : 1.0 / p->tau;
   for (int d = 0; d < 3; ++d) c->ph.F[d] = p->force[d];
   c->ph.scale = p->storage == LBM_F16 ? std::ldexp(1.0, p->f16_scale_log2) : 1.0;
+  for (int d = 0; d < 3; ++d) c->ph.wall_u[d] = p->wall_u[d];
+  c->ph.moving =
+      flags != nullptr && (p->wall_u[0] != 0.0 || p->wall_u[1] != 0.0 || p->wall_u[2] != 0.0);
+  c->ph.incomp = p->equilibrium == LBM_EQ_INCOMPRESSIBLE;
   c->grid[0] = grid_a;
   c->grid[1] = grid_b;
   c->flags = flags;
@@ -241,7 +250,7 @@ lbm_status lbm_refresh_solids(lbm_ctx* c) {
   if (st != LBM_OK) return st;
   if (!c->flags) return LBM_OK;
   hipError_t e =
-      lbm::launch_mark_solids(c->p.storage, c->geo, c->grid[c->cur], c->flags, c->stream);
+      lbm::launch_mark_solids(c->p.storage, c->geo, c->ph, c->grid[c->cur], c->flags, c->stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "solid marker launch");
 }
 
@@ -325,7 +334,7 @@ lbm_status lbm_adjoint_init(lbm_ctx* c, const float* lam_0, const float* rho0, c
   lbm_status st = adj_check(c);
   if (st != LBM_OK) return st;
   if (!lam_0 || !dL_du0) return fail(LBM_E_ARG, "lam_0 and dL_du0 must not be NULL");
-  hipError_t e = lbm::launch_adj_init(c->geo, c->flags, lam_0, rho0, u0, dL_du0, c->stream);
+  hipError_t e = lbm::launch_adj_init(c->geo, c->ph, c->flags, lam_0, rho0, u0, dL_du0, c->stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint init launch");
 }
 

@@ -74,6 +74,7 @@ __host__ __device__ constexpr C coef_q(int i) {
 
 constexpr uint8_t FLAG_SOLID = 1;
 constexpr uint8_t FLAG_NOFORCE = 2;
+constexpr uint8_t FLAG_MOVING = 4;  // with FLAG_SOLID: a wall cell moving with the wall velocity
 
 // Storage formats of the population offset g = f - w.  `load` widens a stored
 // element to the compute type, `store` rounds to nearest-even.

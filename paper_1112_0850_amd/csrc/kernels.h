@@ -26,9 +26,12 @@ constexpr int kBlock = 256;
 constexpr int kReduceBlocks = 1024;
 
 struct PhysParams {
-  double omega;     // 1 / tau (0 for tau = +inf)
-  double F[3];      // body-force density
-  double scale;     // FP16 storage scale 2^s (1 otherwise)
+  double omega;      // 1 / tau (0 for tau = +inf)
+  double F[3];       // body-force density
+  double scale;      // FP16 storage scale 2^s (1 otherwise)
+  double wall_u[3];  // velocity of the moving-wall cells
+  bool moving;       // wall_u != 0 and the grid has flags: moving-wall markers are in use
+  bool incomp;       // He-Luo incompressible equilibrium (u = j + F/2)
 };
 
 Geo make_geo(int nx, int ny, int nz, int xs);
@@ -36,8 +39,8 @@ Geo make_geo(int nx, int ny, int nz, int xs);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_init(int storage, const Geo& g, const PhysParams& ph, void* grid,
                        const uint8_t* flags, const float* rho0, const float* u0, hipStream_t s);
-hipError_t launch_mark_solids(int storage, const Geo& g, void* grid, const uint8_t* flags,
-                              hipStream_t s);
+hipError_t launch_mark_solids(int storage, const Geo& g, const PhysParams& ph, void* grid,
+                              const uint8_t* flags, hipStream_t s);
 hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
                        const void* src, void* dst, const uint8_t* flags, hipStream_t s);
 hipError_t launch_macro(int storage, bool out_f64, const Geo& g, const PhysParams& ph,
@@ -50,8 +53,8 @@ hipError_t launch_adj_seed(const Geo& g, const PhysParams& ph, const float* fT, 
 hipError_t launch_adj_step(bool solids, const Geo& g, const PhysParams& ph, const float* fn,
                            const uint8_t* flags, const float* lam_np1, float* lam_n,
                            double* partials, hipStream_t s);
-hipError_t launch_adj_init(const Geo& g, const uint8_t* flags, const float* lam0, const float* rho0,
-                           const float* u0, float* dL_du0, hipStream_t s);
+hipError_t launch_adj_init(const Geo& g, const PhysParams& ph, const uint8_t* flags, const float* lam0,
+                           const float* rho0, const float* u0, float* dL_du0, hipStream_t s);
 hipError_t launch_adj_finish(const Geo& g, const double* partials, double* out3, hipStream_t s);
 hipError_t launch_copy(void* c, const void* a, size_t n16, hipStream_t s);
 

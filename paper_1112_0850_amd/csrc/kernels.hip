@@ -20,6 +20,9 @@
 //   S_i = (1 - omega/2) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F       (Guo 2002),
 //   g*_i = (1 - omega) g_i + omega g^eq_i + S_i.
 // The second form of g^eq never rounds rho = 1 + delta_rho (see collide()).
+// With the incompressible equilibrium of He & Luo (rho0 = 1) u = j' and the
+// same coefficient form holds with t = 0 below.  Walls moving with u_w add
+// 6 w_i (c_i.u_w) to each bounced-back population (Ladd 1994, rho0 = 1).
 #include "d3q19.h"
 #include "kernels.h"
 
@@ -46,7 +49,17 @@ struct Phys {
   C F[3];
   C scale;
   C inv_scale;
+  C Kw[Q];     // moving-wall term 6 w_i (c_i.u_w) of a bounced-back population (unscaled)
+  int moving;  // moving-wall markers in use
+  int incomp;  // incompressible equilibrium
 };
+
+// 6 w_i (c_i.u_w): what the half-way bounce-back of direction i gains from a
+// wall cell moving with u_w (pull form: the population arriving along c_i).
+static double wall_term(int i, const double* uw) {
+  return 6.0 * weight<double>(i) *
+         (D3Q19::cx[i] * uw[0] + D3Q19::cy[i] * uw[1] + D3Q19::cz[i] * uw[2]);
+}
 
 template <typename C>
 static Phys<C> to_phys(const PhysParams& p) {
@@ -55,7 +68,17 @@ static Phys<C> to_phys(const PhysParams& p) {
   for (int d = 0; d < 3; ++d) r.F[d] = C(p.F[d]);
   r.scale = C(p.scale);
   r.inv_scale = C(1.0 / p.scale);
+  for (int i = 0; i < Q; ++i) r.Kw[i] = C(wall_term(i, p.wall_u));
+  r.moving = p.moving ? 1 : 0;
+  r.incomp = p.incomp ? 1 : 0;
   return r;
+}
+
+// Marker of a solid cell: a quiet NaN, or +infinity for a moving-wall cell
+// while moving-wall markers are in use.
+template <typename C>
+__device__ __forceinline__ C solid_marker(uint8_t fl, bool moving) {
+  return (moving && (fl & FLAG_MOVING)) ? C(__builtin_inf()) : C(__builtin_nan(""));
 }
 
 // ---------------------------------------------------------------------------
@@ -194,6 +217,7 @@ struct StepK {
   C K3W[3];      // 3 (1 - omega/2) W S     (Guo, -3 W u.F part)
   C Kq[9];       // (1 - omega/2) q (c.F) S (Guo, 9 W (c.u)(c.F) part)
   C Ka[9];       // (1 - omega/2) a (c.F) S (Guo, 3 W c.F part)
+  C Kw[Q];       // 6 w_i (c_i.u_w) S      (moving-wall bounce-back term)
 };
 
 // BGK relaxation towards the Qian equilibrium with Guo forcing, in place, in
@@ -203,8 +227,9 @@ struct StepK {
 //   g*_i   = (1 - omega) g_i + omega g^eq_i + S_i.
 // The momentum-carrying term is omega * (a_i c_i.j') with the conservation-
 // exact a_i, so the collision keeps sum g* c = j + F without a rounding bias
-// from the constants.  `fon` is 1 (forced cell) or 0 (no-force cell).
-template <typename C, bool FORCE, bool SCALED>
+// from the constants.  `fon` is 1 (forced cell) or 0 (no-force cell).  INC:
+// the incompressible equilibrium, u = j' (rho0 = 1).
+template <typename C, bool FORCE, bool SCALED, bool INC>
 __device__ __forceinline__ void collide(C* f, const StepK<C>& k, C fon) {
   const C d1 = f[1] - f[2], d3 = f[3] - f[4], d5 = f[5] - f[6], d7 = f[7] - f[8],
           d9 = f[9] - f[10], d11 = f[11] - f[12], d13 = f[13] - f[14], d15 = f[15] - f[16],
@@ -220,8 +245,13 @@ __device__ __forceinline__ void collide(C* f, const StepK<C>& k, C fon) {
     jy += fon * k.Fh[1];
     jz += fon * k.Fh[2];
   }
-  const C t = step_t_factor(drho, SCALED ? k.S : C(1));
-  C ux = jx - jx * t, uy = jy - jy * t, uz = jz - jz * t;
+  C ux = jx, uy = jy, uz = jz;
+  if (!INC) {
+    const C t = step_t_factor(drho, SCALED ? k.S : C(1));
+    ux = jx - jx * t;
+    uy = jy - jy * t;
+    uz = jz - jz * t;
+  }
   if (SCALED) {
     ux *= k.invS;
     uy *= k.invS;
@@ -262,15 +292,21 @@ __device__ __forceinline__ void collide(C* f, const StepK<C>& k, C fon) {
 // its own slots, which keeps every store instruction a full, coalesced line
 // (partially written lines cost far more HBM time than their bytes).  The
 // flags are read only for the solid test and the per-cell force switch.
+//
+// WALLS: 0 = no solid cells, 1 = solid cells at rest, 2 = moving walls as
+// well.  In the last case a moving-wall cell's marker is +infinity instead
+// of NaN, and a bounced-back value whose pull returned infinity gains the
+// wall term 6 w_i (c_i.u_w) -- the moving wall costs nothing away from it.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void stream_store(T* p, T v) {
   __builtin_nontemporal_store(v, p);
 }
 
-template <typename C>
+template <int WALLS, typename C>
 __device__ __forceinline__ bool is_marker(C v) {
-  return v != v;  // NaN
+  if (WALLS == 2) return !__builtin_isfinite(v);  // NaN or infinity
+  return v != v;                                   // NaN
 }
 
 // Cells per lane of the step kernel: a wave owns a run of 64*M cells of one
@@ -282,7 +318,7 @@ struct StepCells {
   static constexpr int M = (K == ST_F16 || K == ST_BF16) ? 4 : 1;
 };
 
-template <int K, bool SOLIDS, bool FORCE, int M>
+template <int K, int WALLS, bool FORCE, bool INC, int M>
 __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* __restrict__ src,
                                                  typename Storage<K>::T* __restrict__ dst,
                                                  const uint8_t* __restrict__ flags, Geo g,
@@ -290,6 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
   using C = typename Storage<K>::C;
   using T = typename Storage<K>::T;
   constexpr bool SCALED = (K == ST_F16);
+  constexpr bool SOLIDS = WALLS != 0;
   // g describes 64*M-cell segments (step_geo); same block remap as locate().
   const int b = blockIdx.x;
   const int lb = (b < g.nb8) ? ((b & 7) * (g.nb8 >> 3) + (b >> 3)) : b;
@@ -327,17 +364,21 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
     if (SOLIDS) {
 #pragma unroll
       for (int i = 1; i < Q; ++i)
-        if (is_marker(f[m][i]) && !solid[m]) f[m][i] = C(*elem(src, pb, D3Q19::opp[i], n[m].own));
+        if (is_marker<WALLS>(f[m][i]) && !solid[m]) {
+          C b = C(*elem(src, pb, D3Q19::opp[i], n[m].own));
+          if (WALLS == 2 && __builtin_isinf(f[m][i])) b += k.Kw[i];
+          f[m][i] = b;
+        }
     }
   }
-  const C marker = C(__builtin_nan(""));
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     // Solid lanes run the collision on their (meaningless) pulls and discard it.
     if (FORCE && SOLIDS)
-      collide<C, FORCE, SCALED>(f[m], k, (fl[m] & FLAG_NOFORCE) ? C(0) : C(1));
+      collide<C, FORCE, SCALED, INC>(f[m], k, (fl[m] & FLAG_NOFORCE) ? C(0) : C(1));
     else
-      collide<C, FORCE, SCALED>(f[m], k, C(1));
+      collide<C, FORCE, SCALED, INC>(f[m], k, C(1));
+    const C marker = solid_marker<C>(fl[m], WALLS == 2);
     if (valid[m]) {
 #pragma unroll
       for (int i = 0; i < Q; ++i)
@@ -349,16 +390,19 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 // Writes the solid marker into every slot of the solid cells of a grid.
 template <int K>
 __global__ __launch_bounds__(kBlock) void k_mark_solids(typename Storage<K>::T* __restrict__ grid,
-                                                        const uint8_t* __restrict__ flags, Geo g) {
+                                                        const uint8_t* __restrict__ flags, Geo g,
+                                                        int moving) {
   using T = typename Storage<K>::T;
   using C = typename Storage<K>::C;
   const Loc l = locate(g);
   if (!l.valid) return;
   const Nbhd n = neighbourhood(g, l);
-  if (!(flags[n.fown] & FLAG_SOLID)) return;
+  const uint8_t fl = flags[n.fown];
+  if (!(fl & FLAG_SOLID)) return;
   const size_t pb = size_t(g.plane) * sizeof(T);
+  const T marker = T(solid_marker<C>(fl, moving != 0));
 #pragma unroll
-  for (int i = 0; i < Q; ++i) *elem(grid, pb, i, n.own) = T(C(__builtin_nan("")));
+  for (int i = 0; i < Q; ++i) *elem(grid, pb, i, n.own) = marker;
 }
 
 // ---------------------------------------------------------------------------
@@ -378,8 +422,9 @@ __global__ __launch_bounds__(kBlock) void k_init(typename Storage<K>::T* __restr
   const uint32_t c = n.fown;
   const size_t pb = size_t(g.plane) * sizeof(T);
   if (flags && (flags[c] & FLAG_SOLID)) {  // solid marker
+    const T marker = T(solid_marker<C>(flags[c], ph.moving != 0));
 #pragma unroll
-    for (int i = 0; i < Q; ++i) *elem(grid, pb, i, n.own) = T(C(__builtin_nan("")));
+    for (int i = 0; i < Q; ++i) *elem(grid, pb, i, n.own) = marker;
     return;
   }
   const size_t ncell = size_t(g.nx) * g.ny * g.nz;
@@ -390,9 +435,11 @@ __global__ __launch_bounds__(kBlock) void k_init(typename Storage<K>::T* __restr
     uy = C(u0[ncell + c]);
     uz = C(u0[2 * ncell + c]);
   }
-  // f^eq(rho0, u0) - w in the collision's coefficient form, j' = rho0 u0.
+  // f^eq(rho0, u0) - w in the collision's coefficient form, j' = rho0 u0
+  // (j' = u0 for the incompressible equilibrium).
   const C drho = rho - C(1);
-  const C jx = rho * ux, jy = rho * uy, jz = rho * uz;
+  const C jx = ph.incomp ? ux : rho * ux, jy = ph.incomp ? uy : rho * uy,
+          jz = ph.incomp ? uz : rho * uz;
   const C base = drho - C(1.5) * (jx * ux + jy * uy + jz * uz);
   C f[Q];
   f[0] = coef_W<C>(0) * base;
@@ -411,13 +458,14 @@ __global__ __launch_bounds__(kBlock) void k_init(typename Storage<K>::T* __restr
 
 // ---------------------------------------------------------------------------
 // Macroscopic fields from the stored post-collision state:
-// rho = 1 + sum g*_i, rho u = sum g*_i c_i - F/2.
+// rho = 1 + sum g*_i, rho u = sum g*_i c_i - F/2 (rho0 u, rho0 = 1, for the
+// incompressible equilibrium).
 // ---------------------------------------------------------------------------
 template <int K, typename O>
 __global__ __launch_bounds__(kBlock) void k_macro(const typename Storage<K>::T* __restrict__ grid,
                                                   const uint8_t* __restrict__ flags,
                                                   O* __restrict__ rho_out, O* __restrict__ u_out,
-                                                  Geo g, O Fx, O Fy, O Fz, O inv_scale) {
+                                                  Geo g, O Fx, O Fy, O Fz, O inv_scale, int incomp) {
   const Loc l = locate(g);
   if (!l.valid) return;
   const uint32_t c = uint32_t((l.z * g.ny + l.y) * g.nx + l.x);
@@ -435,11 +483,16 @@ __global__ __launch_bounds__(kBlock) void k_macro(const typename Storage<K>::T* 
     moments(f, drho, jx, jy, jz);
     if (fl & FLAG_NOFORCE) Fx = Fy = Fz = O(0);
     r = O(1) + drho;
-    const O t = inv_rho_factor(drho);
     const O mx = jx - O(0.5) * Fx, my = jy - O(0.5) * Fy, mz = jz - O(0.5) * Fz;
-    ux = mx - mx * t;
-    uy = my - my * t;
-    uz = mz - mz * t;
+    ux = mx;
+    uy = my;
+    uz = mz;
+    if (!incomp) {
+      const O t = inv_rho_factor(drho);
+      ux = mx - mx * t;
+      uy = my - my * t;
+      uz = mz - mz * t;
+    }
   }
   if (rho_out) rho_out[c] = r;
   if (u_out) {
@@ -474,7 +527,8 @@ template <int K>
 __global__ __launch_bounds__(kBlock) void k_reduce_partials(const typename Storage<K>::T* __restrict__ grid,
                                                             const uint8_t* __restrict__ flags, Geo g,
                                                             double Fx, double Fy, double Fz,
-                                                            double inv_scale, double* __restrict__ out) {
+                                                            double inv_scale, int incomp,
+                                                            double* __restrict__ out) {
   __shared__ double sh[5 * kBlock];
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   const int64_t ncell = int64_t(g.nx) * g.ny * g.nz;
@@ -498,7 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_partials(const typename Stora
     acc[1] += px;
     acc[2] += py;
     acc[3] += pz;
-    acc[4] += 0.5 * (px * px + py * py + pz * pz) / rho;
+    acc[4] += 0.5 * (px * px + py * py + pz * pz) / (incomp ? 1.0 : rho);
   }
   block_sum<5>(acc, sh);
   if (threadIdx.x == 0)
@@ -530,6 +584,10 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restric
 //   b  = omega rho (3 L1 + 9 L2 u - 3 u L0) + (1 - omega/2)(9 L2 F - 3 F L0)
 //   mu_j = (1 - omega) lam_j + a + b . (c_j - u) / rho
 //   dL/dF += (1 - omega/2)(3 L1 - 3 u L0 + 9 L2 u) + b / (2 rho)
+// With the incompressible equilibrium (u = j', d f^eq_i / d rho = w_i) the
+// same holds with a = omega L0, rho -> 1 in b and in b/(2 rho), and
+// mu_j = (1 - omega) lam_j + a + b . c_j.  A moving wall adds a constant to
+// the streaming, which enters the recomputed state only.
 // ---------------------------------------------------------------------------
 struct LamMoments {
   float L0, L1x, L1y, L1z, Lxx, Lyy, Lzz, Lxy, Lxz, Lyz;
@@ -563,7 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(const float* __restrict__ f
                                                      const float* __restrict__ gu,
                                                      float* __restrict__ lam,
                                                      double* __restrict__ partials, Geo g,
-                                                     float Fx, float Fy, float Fz) {
+                                                     float Fx, float Fy, float Fz, int incomp) {
   __shared__ double sh[3 * kBlock];
   double d[3] = {0.0, 0.0, 0.0};
   const Loc l = locate(g);
@@ -583,8 +641,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(const float* __restrict__ f
       moments(f, drho, jx, jy, jz);
       const bool forced = !(fl & FLAG_NOFORCE);
       const float h = forced ? 0.5f : 0.0f;
-      const float rho = 1.0f + drho;
-      const float ux = (jx - h * Fx) / rho, uy = (jy - h * Fy) / rho, uz = (jz - h * Fz) / rho;
+      const float rho_u = incomp ? 1.0f : 1.0f + drho;  // the density dividing j in u
+      const float ux = (jx - h * Fx) / rho_u, uy = (jy - h * Fy) / rho_u,
+                  uz = (jz - h * Fz) / rho_u;
       const float G = gr ? gr[c] : 0.0f;
       float gx = 0.0f, gy = 0.0f, gz = 0.0f;
       if (gu) {
@@ -592,14 +651,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_seed(const float* __restrict__ f
         gy = gu[ncell + c];
         gz = gu[2 * ncell + c];
       }
-      const float hx = gx / rho, hy = gy / rho, hz = gz / rho;
-      const float base = G - (hx * ux + hy * uy + hz * uz);
+      const float hx = gx / rho_u, hy = gy / rho_u, hz = gz / rho_u;
+      const float base = incomp ? G : G - (hx * ux + hy * uy + hz * uz);
 #pragma unroll
       for (int i = 0; i < Q; ++i) lam[size_t(i) * g.plane + own] = base + cdot<float>(i, hx, hy, hz);
       if (forced) {
-        d[0] = -double(gx) / (2.0 * double(rho));
-        d[1] = -double(gy) / (2.0 * double(rho));
-        d[2] = -double(gz) / (2.0 * double(rho));
+        d[0] = -double(gx) / (2.0 * double(rho_u));
+        d[1] = -double(gy) / (2.0 * double(rho_u));
+        d[2] = -double(gz) / (2.0 * double(rho_u));
       }
     }
   }
@@ -622,10 +681,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(const float* __restrict__ f
     const Nbhd n = neighbourhood(g, l);
     const uint8_t fl = SOLIDS ? flags[n.fown] : uint8_t(0);
     if (!(fl & FLAG_SOLID)) {
-      bool bb[Q];
+      bool bb[Q], mv[Q];
 #pragma unroll
-      for (int i = 0; i < Q; ++i)
-        bb[i] = SOLIDS && i != 0 && (flags[src_foff(n, i)] & FLAG_SOLID);
+      for (int i = 0; i < Q; ++i) {
+        const uint8_t nf = (SOLIDS && i != 0) ? flags[src_foff(n, i)] : uint8_t(0);
+        bb[i] = nf & FLAG_SOLID;
+        mv[i] = ph.moving && bb[i] && (nf & FLAG_MOVING);
+      }
       // recompute the pre-collision state f(n+1) = stream(f*(n))
       float f[Q];
 #pragma unroll
@@ -633,6 +695,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(const float* __restrict__ f
         const float* p = fn + size_t(i) * g.plane + src_off(n, i);
         if (SOLIDS && i != 0) p = bb[i] ? fn + size_t(D3Q19::opp[i]) * g.plane + n.own : p;
         f[i] = *p;
+        if (SOLIDS && mv[i]) f[i] += ph.Kw[i];
       }
       float lam[Q];
 #pragma unroll
@@ -642,8 +705,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(const float* __restrict__ f
                   Fz = forced ? ph.F[2] : 0.0f;
       float drho, jx, jy, jz;
       moments(f, drho, jx, jy, jz);
-      const float rho = 1.0f + drho;
-      const float inv_rho = 1.0f / rho;
+      const bool inc = ph.incomp != 0;
+      const float rho = inc ? 1.0f : 1.0f + drho;  // the density dividing j' in u
+      const float inv_rho = inc ? 1.0f : 1.0f / rho;
       const float ux = (jx + 0.5f * Fx) * inv_rho, uy = (jy + 0.5f * Fy) * inv_rho,
                   uz = (jz + 0.5f * Fz) * inv_rho;
       const float om = ph.omega, om1 = 1.0f - om, fpre = 1.0f - 0.5f * om;
@@ -656,8 +720,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(const float* __restrict__ f
       const float LFy = m.Lxy * Fx + m.Lyy * Fy + m.Lyz * Fz;
       const float LFz = m.Lxz * Fx + m.Lyz * Fy + m.Lzz * Fz;
       const float uu = ux * ux + uy * uy + uz * uz;
-      const float a = om * (m.L0 + 3.0f * (m.L1x * ux + m.L1y * uy + m.L1z * uz) +
-                            4.5f * (ux * Lux + uy * Luy + uz * Luz) - 1.5f * uu * m.L0);
+      const float a = inc ? om * m.L0
+                          : om * (m.L0 + 3.0f * (m.L1x * ux + m.L1y * uy + m.L1z * uz) +
+                                  4.5f * (ux * Lux + uy * Luy + uz * Luz) - 1.5f * uu * m.L0);
       const float orho = om * rho;
       const float bx = orho * (3.0f * m.L1x + 9.0f * Lux - 3.0f * ux * m.L0) +
                        fpre * (9.0f * LFx - 3.0f * Fx * m.L0);
@@ -666,7 +731,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(const float* __restrict__ f
       const float bz = orho * (3.0f * m.L1z + 9.0f * Luz - 3.0f * uz * m.L0) +
                        fpre * (9.0f * LFz - 3.0f * Fz * m.L0);
       const float bhx = bx * inv_rho, bhy = by * inv_rho, bhz = bz * inv_rho;
-      const float a0 = a - (bhx * ux + bhy * uy + bhz * uz);
+      const float a0 = inc ? a : a - (bhx * ux + bhy * uy + bhz * uz);
       // transposed streaming: push mu_i to the pull source of direction i
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
@@ -688,11 +753,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_step(const float* __restrict__ f
 }
 
 // dL/du0 = sum_i lam0_i w_i rho0 (3 c_i + 9 (c_i.u0) c_i - 3 u0) = rho0 (3 L1 + 9 L2 u0 - 3 u0 L0).
+// (rho0 -> 1 in the prefactor for the incompressible equilibrium.)
 __global__ __launch_bounds__(kBlock) void k_adj_init(const float* __restrict__ lam0,
                                                      const uint8_t* __restrict__ flags,
                                                      const float* __restrict__ rho0,
                                                      const float* __restrict__ u0,
-                                                     float* __restrict__ du0, Geo g) {
+                                                     float* __restrict__ du0, Geo g, int incomp) {
   const Loc l = locate(g);
   if (!l.valid) return;
   const uint32_t c = uint32_t((l.z * g.ny + l.y) * g.nx + l.x);
@@ -704,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_init(const float* __restrict__ l
 #pragma unroll
     for (int i = 0; i < Q; ++i) lam[i] = lam0[size_t(i) * g.plane + own];
     const LamMoments m = lam_moments(lam);
-    const float rho = rho0 ? rho0[c] : 1.0f;
+    const float rho = (rho0 && !incomp) ? rho0[c] : 1.0f;
     float ux = 0.0f, uy = 0.0f, uz = 0.0f;
     if (u0) {
       ux = u0[c];
@@ -786,19 +852,20 @@ hipError_t launch_init(int storage, const Geo& g, const PhysParams& ph, void* gr
 }
 
 template <int K>
-static void mark_t(const Geo& g, void* grid, const uint8_t* flags, hipStream_t s) {
+static void mark_t(const Geo& g, bool moving, void* grid, const uint8_t* flags, hipStream_t s) {
   hipLaunchKernelGGL(k_mark_solids<K>, dim3(g.nblocks), dim3(kBlock), 0, s,
-                     reinterpret_cast<typename Storage<K>::T*>(grid), flags, g);
+                     reinterpret_cast<typename Storage<K>::T*>(grid), flags, g, moving ? 1 : 0);
 }
 
-hipError_t launch_mark_solids(int storage, const Geo& g, void* grid, const uint8_t* flags,
-                              hipStream_t s) {
+hipError_t launch_mark_solids(int storage, const Geo& g, const PhysParams& ph, void* grid,
+                              const uint8_t* flags, hipStream_t s) {
+  const bool mv = ph.moving;
   switch (storage) {
-    case ST_F32: mark_t<ST_F32>(g, grid, flags, s); break;
-    case ST_F16: mark_t<ST_F16>(g, grid, flags, s); break;
-    case ST_BF16: mark_t<ST_BF16>(g, grid, flags, s); break;
-    case ST_F64: mark_t<ST_F64>(g, grid, flags, s); break;
-    case ST_F32X: mark_t<ST_F32X>(g, grid, flags, s); break;
+    case ST_F32: mark_t<ST_F32>(g, mv, grid, flags, s); break;
+    case ST_F16: mark_t<ST_F16>(g, mv, grid, flags, s); break;
+    case ST_BF16: mark_t<ST_BF16>(g, mv, grid, flags, s); break;
+    case ST_F64: mark_t<ST_F64>(g, mv, grid, flags, s); break;
+    case ST_F32X: mark_t<ST_F32X>(g, mv, grid, flags, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -831,6 +898,7 @@ static StepK<C> make_stepk(const PhysParams& p) {
     k.Kq[q] = C(fpre * 9.0 * weight<double>(i) * cF * S);
     k.Ka[q] = C(fpre * 3.0 * weight<double>(i) * cF * S);
   }
+  for (int i = 0; i < Q; ++i) k.Kw[i] = C(wall_term(i, p.wall_u) * S);
   return k;
 }
 
@@ -844,28 +912,38 @@ static Geo step_geo(const Geo& g, int M) {
   return h;
 }
 
-template <int K, bool SOLIDS, bool FORCE>
+template <int K, int WALLS, bool FORCE, bool INC>
 static void step_t(const Geo& g, const PhysParams& ph, const void* src, void* dst,
                    const uint8_t* flags, hipStream_t s) {
   using S = Storage<K>;
   constexpr int M = StepCells<K>::M;
   const Geo h = step_geo(g, M);
-  hipLaunchKernelGGL((k_step<K, SOLIDS, FORCE, M>), dim3(h.nblocks), dim3(kBlock), 0, s,
+  hipLaunchKernelGGL((k_step<K, WALLS, FORCE, INC, M>), dim3(h.nblocks), dim3(kBlock), 0, s,
                      reinterpret_cast<const typename S::T*>(src),
                      reinterpret_cast<typename S::T*>(dst), flags, h,
                      make_stepk<typename S::C>(ph));
 }
 
+template <int K, int WALLS, bool INC>
+static void step_f(bool force, const Geo& g, const PhysParams& ph, const void* src, void* dst,
+                   const uint8_t* flags, hipStream_t s) {
+  if (force) step_t<K, WALLS, true, INC>(g, ph, src, dst, flags, s);
+  else step_t<K, WALLS, false, INC>(g, ph, src, dst, flags, s);
+}
+
+template <int K, bool INC>
+static void step_w(bool solids, bool force, const Geo& g, const PhysParams& ph, const void* src,
+                   void* dst, const uint8_t* flags, hipStream_t s) {
+  if (!solids) step_f<K, 0, INC>(force, g, ph, src, dst, flags, s);
+  else if (!ph.moving) step_f<K, 1, INC>(force, g, ph, src, dst, flags, s);
+  else step_f<K, 2, INC>(force, g, ph, src, dst, flags, s);
+}
+
 template <int K>
 static void step_k(bool solids, bool force, const Geo& g, const PhysParams& ph, const void* src,
                    void* dst, const uint8_t* flags, hipStream_t s) {
-  if (solids) {
-    if (force) step_t<K, true, true>(g, ph, src, dst, flags, s);
-    else step_t<K, true, false>(g, ph, src, dst, flags, s);
-  } else {
-    if (force) step_t<K, false, true>(g, ph, src, dst, flags, s);
-    else step_t<K, false, false>(g, ph, src, dst, flags, s);
-  }
+  if (ph.incomp) step_w<K, true>(solids, force, g, ph, src, dst, flags, s);
+  else step_w<K, false>(solids, force, g, ph, src, dst, flags, s);
 }
 
 hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
@@ -887,7 +965,7 @@ static void macro_t(const Geo& g, const PhysParams& ph, const void* grid, const 
   hipLaunchKernelGGL((k_macro<K, O>), dim3(g.nblocks), dim3(kBlock), 0, s,
                      reinterpret_cast<const typename Storage<K>::T*>(grid), flags,
                      reinterpret_cast<O*>(rho), reinterpret_cast<O*>(u), g, O(ph.F[0]),
-                     O(ph.F[1]), O(ph.F[2]), O(1.0 / ph.scale));
+                     O(ph.F[1]), O(ph.F[2]), O(1.0 / ph.scale), ph.incomp ? 1 : 0);
 }
 
 template <typename O>
@@ -915,7 +993,7 @@ static void reduce_t(const Geo& g, const PhysParams& ph, const void* grid, const
                      double* scratch, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_partials<K>, dim3(kReduceBlocks), dim3(kBlock), 0, s,
                      reinterpret_cast<const typename Storage<K>::T*>(grid), flags, g, ph.F[0],
-                     ph.F[1], ph.F[2], 1.0 / ph.scale, scratch);
+                     ph.F[1], ph.F[2], 1.0 / ph.scale, ph.incomp ? 1 : 0, scratch);
 }
 
 hipError_t launch_reduce(int storage, const Geo& g, const PhysParams& ph, const void* grid,
@@ -938,7 +1016,8 @@ hipError_t launch_adj_seed(const Geo& g, const PhysParams& ph, const float* fT, 
                            const float* dL_drho, const float* dL_du, float* lam, double* partials,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_adj_seed, dim3(g.nblocks), dim3(kBlock), 0, s, fT, flags, dL_drho, dL_du,
-                     lam, partials, g, float(ph.F[0]), float(ph.F[1]), float(ph.F[2]));
+                     lam, partials, g, float(ph.F[0]), float(ph.F[1]), float(ph.F[2]),
+                     ph.incomp ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -954,10 +1033,10 @@ hipError_t launch_adj_step(bool solids, const Geo& g, const PhysParams& ph, cons
   return hipGetLastError();
 }
 
-hipError_t launch_adj_init(const Geo& g, const uint8_t* flags, const float* lam0, const float* rho0,
-                           const float* u0, float* dL_du0, hipStream_t s) {
+hipError_t launch_adj_init(const Geo& g, const PhysParams& ph, const uint8_t* flags, const float* lam0,
+                           const float* rho0, const float* u0, float* dL_du0, hipStream_t s) {
   hipLaunchKernelGGL(k_adj_init, dim3(g.nblocks), dim3(kBlock), 0, s, lam0, flags, rho0, u0,
-                     dL_du0, g);
+                     dL_du0, g, ph.incomp ? 1 : 0);
   return hipGetLastError();
 }
 

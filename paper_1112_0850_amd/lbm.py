@@ -14,6 +14,7 @@ from . import _abi as A
 
 STORAGE = {"f32": A.LBM_F32, "f16": A.LBM_F16, "bf16": A.LBM_BF16, "f64": A.LBM_F64,
            "f32x": A.LBM_F32X}
+EQUILIBRIUM = {"qian": A.LBM_EQ_QIAN, "incompressible": A.LBM_EQ_INCOMPRESSIBLE}
 TORCH_DTYPE = {A.LBM_F32: torch.float32, A.LBM_F16: torch.float16,
                A.LBM_BF16: torch.bfloat16, A.LBM_F64: torch.float64, A.LBM_F32X: torch.float32}
 
@@ -42,10 +43,13 @@ def _as_field(x, shape, dtype, device, what):
 class LBM:
     """One D3Q19 BGK simulation on a periodic box (walls and obstacles are
     solid flag bits).  ``storage`` in {'f32', 'f16', 'bf16', 'f64', 'f32x'}
-    ('f32x': FP32 storage with FP64 collision arithmetic)."""
+    ('f32x': FP32 storage with FP64 collision arithmetic).  ``wall_u``: the
+    velocity of the cells flagged solid + moving (bit 2); ``equilibrium``:
+    'qian' (u = j/rho) or 'incompressible' (He-Luo, u = j/rho0)."""
 
     def __init__(self, shape, tau, force=(0.0, 0.0, 0.0), storage="f32", flags=None, u0=None,
-                 rho0=None, f16_scale_log2=0, x_align=0, device="cuda"):
+                 rho0=None, f16_scale_log2=0, x_align=0, device="cuda", wall_u=(0.0, 0.0, 0.0),
+                 equilibrium="qian"):
         self.shape = tuple(int(s) for s in shape)
         if len(self.shape) != 3:
             raise ValueError("shape must be (nz, ny, nx)")
@@ -58,7 +62,11 @@ class LBM:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.tau = float(tau)
         self.force = tuple(float(f) for f in force)
-        self.params = A.params(self.shape, tau, self.force, self.storage, f16_scale_log2, x_align)
+        self.wall_u = tuple(float(v) for v in wall_u)
+        self.equilibrium = EQUILIBRIUM[equilibrium] if isinstance(equilibrium, str) \
+            else int(equilibrium)
+        self.params = A.params(self.shape, tau, self.force, self.storage, f16_scale_log2, x_align,
+                               self.wall_u, self.equilibrium)
         xs, gb, sb, ab = A.lbm_query(self.params)
         self.x_stride, self.grid_bytes, self.adj_partials_bytes = xs, gb, ab
         nz, ny, nx = self.shape
@@ -160,9 +168,10 @@ class _Rollout(torch.autograd.Function):
     checkpoints every k steps and recomputation inside each segment."""
 
     @staticmethod
-    def forward(ctx, u0, g, steps, tau, flags, k):
+    def forward(ctx, u0, g, steps, tau, flags, k, wall_u, equilibrium):
         force = [float(v) for v in g.detach().double().cpu().tolist()]
-        sim = LBM(u0.shape[1:], tau, force, "f32", flags=flags, u0=u0.detach(), device=u0.device)
+        sim = LBM(u0.shape[1:], tau, force, "f32", flags=flags, u0=u0.detach(), device=u0.device,
+                  wall_u=wall_u, equilibrium=equilibrium)
         ckpts = []
         for t in range(steps):
             if t % k == 0:
@@ -199,17 +208,20 @@ class _Rollout(torch.autograd.Function):
         dF = torch.empty(3, dtype=torch.float64, device=dev)
         A.lbm_adjoint_finish_dF(sim.ctx, _ptr(partials), _ptr(dF))
         gdt, gdev = ctx.g_meta
-        return du0, dF.to(device=gdev, dtype=gdt), None, None, None, None
+        return du0, dF.to(device=gdev, dtype=gdt), None, None, None, None, None, None
 
 
-def rollout(u0, g, *, steps, tau, flags=None, checkpoint_every=20):
+def rollout(u0, g, *, steps, tau, flags=None, checkpoint_every=20, wall_u=(0.0, 0.0, 0.0),
+            equilibrium="qian"):
     """Differentiable D3Q19 BGK rollout (FP32 storage): returns (rho_T, u_T)
     with gradients for the initial velocity ``u0`` [3, nz, ny, nx] and the
-    body-force density ``g`` [3]."""
+    body-force density ``g`` [3].  Moving walls and the incompressible
+    equilibrium are supported (no gradient for the wall velocity)."""
     if u0.dim() != 4 or u0.shape[0] != 3:
         raise ValueError("u0 must be [3, nz, ny, nx]")
     if g.numel() != 3:
         raise ValueError("g must have 3 components")
     if steps < 1 or checkpoint_every < 1:
         raise ValueError("steps and checkpoint_every must be >= 1")
-    return _Rollout.apply(u0, g.reshape(3), int(steps), float(tau), flags, int(checkpoint_every))
+    return _Rollout.apply(u0, g.reshape(3), int(steps), float(tau), flags, int(checkpoint_every),
+                          tuple(float(v) for v in wall_u), equilibrium)

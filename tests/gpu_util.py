@@ -51,11 +51,14 @@ def f_to_grid(sim, f, offsets=False, flags=None):
 
 
 def check_solids(sim, flags, grid=None):
-    """Every slot of every solid cell holds the NaN marker; returns the
-    offsets with solid cells zeroed (the oracle's convention)."""
+    """Every slot of every solid cell holds its marker (NaN; +infinity for a
+    moving-wall cell when the wall velocity is not zero); returns the offsets
+    with solid cells zeroed (the oracle's convention)."""
     g = grid_to_f(sim, grid, offsets=True, raw=True)
     solid = (flags & 1) == 1
-    assert np.isnan(g[:, solid]).all(), "solid marker missing"
+    moving = solid & ((flags & 4) == 4) & any(v != 0.0 for v in sim.wall_u)
+    assert np.isnan(g[:, solid & ~moving]).all(), "solid marker missing"
+    assert (g[:, moving] == np.inf).all(), "moving-wall marker missing"
     assert np.isfinite(g[:, ~solid]).all(), "non-finite fluid population"
     g[:, solid] = 0.0
     return g

@@ -91,12 +91,26 @@ def test_query_limits():
     (dict(shape=(4, 4, 4), tau=0.6, storage=9), "storage"),
     (dict(shape=(4, 4, 4), tau=0.6, storage=A.LBM_F16, f16_scale_log2=30), "scale"),
     (dict(shape=(4, 4, 4), tau=0.6, x_align=-2), "x_align"),
+    (dict(shape=(4, 4, 4), tau=0.6, wall_u=(0, math.nan, 0)), "wall_u"),
+    (dict(shape=(4, 4, 4), tau=0.6, equilibrium=2), "equilibrium"),
 ])
 def test_invalid_params_rejected(kw, msg):
     with pytest.raises(A.LBMError) as e:
         A.lbm_query(A.params(**kw))
     assert e.value.status == A.LBM_E_ARG
     assert msg in str(e.value)
+
+
+def test_params_layout_and_reserved_field():
+    # six int32, tau, force[3], wall_u[3], equilibrium, reserved: 88 bytes, no padding
+    assert ctypes.sizeof(A.lbm_params) == 88
+    assert A.lbm_params.wall_u.offset == 56 and A.lbm_params.equilibrium.offset == 80
+    p = A.params((4, 4, 4), 0.6, wall_u=(0.1, 0, 0), equilibrium=A.LBM_EQ_INCOMPRESSIBLE)
+    A.lbm_query(p)
+    p.reserved = 1
+    with pytest.raises(A.LBMError) as e:
+        A.lbm_query(p)
+    assert e.value.status == A.LBM_E_ARG and "reserved" in str(e.value)
 
 
 def test_infinite_tau_accepted():

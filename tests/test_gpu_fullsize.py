@@ -1,8 +1,9 @@
 """Parity at the benchmark's full size and launch configuration: the 512^3
-porous box (10% spheres, seed 12345, tau = 0.55, g_x = 1e-6), one fused step
-checked cell by cell on sampled cells, where the oracle recomputes each
-sampled cell from its 3^3 neighbourhood of the previous state; and the
-adjoint kernel at the rollout's 128^3 size, checked on 5^3 neighbourhoods."""
+porous box (10% spheres, seed 12345, tau = 0.55, g_x = 1e-6) and the 512^3
+lid-driven cavity (moving-wall kernel), one fused step checked cell by cell
+on sampled cells, where the oracle recomputes each sampled cell from its
+3^3 neighbourhood of the previous state; and the adjoint kernel at the
+rollout's 128^3 size, checked on 5^3 neighbourhoods."""
 import ctypes
 
 import numpy as np
@@ -49,15 +50,42 @@ def test_sampled_step_at_full_size(geometry, storage, s):
     flags, u0 = geometry
     say(f"full size {N}^3 porous, {storage}: sampled one-step parity")
     sim = LBM((N, N, N), TAU, F, storage, flags=flags, u0=u0, f16_scale_log2=s)
+    rng = np.random.default_rng(2024)
+    fluid = np.flatnonzero((flags & 1 == 0).ravel())
+    _sampled_step(sim, flags, storage, s, rng.choice(fluid, size=256, replace=False), TAU, F, None)
+
+
+CAVITY_TAU, CAVITY_U = 0.55, 0.05
+
+
+@pytest.mark.parametrize("storage,s", [("f32", 0), ("f16", 10)])
+def test_sampled_cavity_step_at_full_size(storage, s):
+    """512^3 lid-driven cavity (top plane moving with (0.05, 0, 0)), after
+    40 steps from rest: cells under the lid (edges and corners included),
+    beside the side walls and at random."""
+    say(f"full size {N}^3 lid-driven cavity, {storage}: sampled one-step parity")
+    flags = I.cavity_flags((N, N, N))
+    sim = LBM((N, N, N), CAVITY_TAU, (0, 0, 0), storage, flags=flags, wall_u=(CAVITY_U, 0, 0),
+              f16_scale_log2=s)
+    sim.step(36)
+    rng = np.random.default_rng(77)
+    zyx = [(N - 2, 1, 1), (N - 2, N - 2, N - 2), (N - 2, 1, N - 2), (N - 2, N // 2, 1),
+           (N - 2, N // 2, N // 2), (1, 1, 1), (N // 2, 1, N // 2)]
+    zyx += [(N - 2, int(a), int(b)) for a, b in rng.integers(1, N - 1, size=(60, 2))]
+    zyx += [tuple(int(v) for v in rng.integers(1, N - 1, size=3)) for _ in range(60)]
+    cells = [(z * N + y) * N + x for z, y, x in zyx]
+    _sampled_step(sim, flags, storage, s, cells, CAVITY_TAU, (0, 0, 0), (CAVITY_U, 0, 0))
+
+
+def _sampled_step(sim, flags, storage, s, cells, tau, F, wall_u):
+    """Three more steps, then one: each sampled fluid cell of the last step
+    against the oracle's step of its 3^3 neighbourhood."""
     sim.step(3)
     prev = sim.save()
     sim.step(1)
     torch.cuda.synchronize()
     pv, cv = sim.grid_view(prev), sim.populations()
     scale = 2.0 ** s
-    rng = np.random.default_rng(2024)
-    fluid = np.flatnonzero((flags & 1 == 0).ravel())
-    cells = rng.choice(fluid, size=256, replace=False)
     worst = 0.0
     gmax = 0.0
     for c in cells:
@@ -67,7 +95,7 @@ def test_sampled_step_at_full_size(geometry, storage, s):
         fl = _fcrop(flags, z, y, x, 1)
         f = g + W[:, None, None, None]
         f[:, fl & 1 == 1] = 0
-        ref = O.step(f, TAU, F, fl, n=1)[:, 1, 1, 1] - W
+        ref = O.step(f, tau, F, fl, n=1, wall_u=wall_u)[:, 1, 1, 1] - W
         got = cv[:, z, y, x].double().cpu().numpy() / scale
         if storage == "f32":
             err = np.abs(got - ref)
