@@ -112,7 +112,7 @@ def large_leg(torch, storage, n, steps=100, warmup=5):
 
 
 def cavity_leg(torch, storage, n, steps, warmup, s=0):
-    """Lid-driven cavity (the paper's verification workload, Sec. 6): n^3 box
+    """Lid-driven cavity (the paper's verification workload, Sec. 7): n^3 box
     with a one-cell solid layer on all faces, the top plane moving with
     (0.05, 0, 0), tau 0.55, from rest -- the moving-wall step kernel."""
     from paper_1112_0850_amd import _abi as A

@@ -8,7 +8,7 @@
  * cells handled by bounce-back (Sec. 2, last paragraph) in its half-way form;
  * body force by Guo, Zheng & Shi (Phys. Rev. E 65, 046308, 2002).  Options:
  * walls moving with one common velocity (the lid of the lid-driven cavity
- * the paper verifies on, Sec. 6), by Ladd's momentum-corrected bounce-back
+ * the paper verifies on, Sec. 7), by Ladd's momentum-corrected bounce-back
  * (J. Fluid Mech. 271, 285, 1994) with reference density 1; and the
  * incompressible equilibrium of He & Luo (J. Stat. Phys. 88, 927, 1997) in
  * place of Qian's (the paper's "incompressible flow solver", abstract and

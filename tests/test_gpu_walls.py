@@ -1,6 +1,6 @@
 """GPU parity of the two model options against the FP64 oracle: walls moving
 with a common velocity (Ladd's corrected half-way bounce-back, reference
-density 1; the lid-driven cavity the paper verifies on, Sec. 6) and the
+density 1; the lid-driven cavity the paper verifies on, Sec. 7) and the
 incompressible equilibrium of He & Luo.  Streaming with moving walls, the
 cavity and the exact steady plane Couette flow in every storage, the
 incompressible Taylor-Green, porous and reduction cases, and the adjoint

@@ -5,7 +5,7 @@ one streaming step transfers, plane Couette flow (whose steady state the
 scheme reproduces exactly: a linear profile has no second derivative for the
 bounce-back slip error to act on), a zero wall velocity reducing to the plain
 bounce-back of the obstacle paragraph (Sec. 2), and the mirror symmetry and
-mass conservation of the lid-driven cavity (Sec. 6)."""
+mass conservation of the lid-driven cavity (Sec. 7)."""
 from fractions import Fraction
 import math
 
