@@ -40,7 +40,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic porous box")
     ap.add_argument("--only", default="",
-                    help="comma list of legs: f32,f16,bf16,f64,f32x,adjoint,copy,cpu,large,cavity")
+                    help="comma list of legs: f32,f16,bf16,f64,f32x,adjoint,copy,cpu,large,cavity,"
+                         "split")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--sweep", action="store_true",
                     help="domain-size sweep instead of the headline run: periodic all-fluid cubes "
@@ -66,10 +67,10 @@ def timed_steps(sim, torch, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s=0):
+def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s=0, **kw):
     from paper_1112_0850_amd import _abi as A
     n = round(n_cells ** (1 / 3))
-    sim = LBM((n, n, n), 0.55, (1e-6, 0.0, 0.0), storage, flags=flags_t, f16_scale_log2=s)
+    sim = LBM((n, n, n), 0.55, (1e-6, 0.0, 0.0), storage, flags=flags_t, f16_scale_log2=s, **kw)
     ms = timed_steps(sim, torch, steps, warmup)
     r = sim.reduce().cpu().numpy()
     bpu = A.lbm_bytes_per_update(sim.storage)
@@ -373,7 +374,8 @@ def main():
         return sweep(torch)
 
     legs = set(args.only.split(",")) if args.only else {"f32", "f16", "bf16", "f64", "f32x",
-                                                        "adjoint", "copy", "cpu", "large", "cavity"}
+                                                        "adjoint", "copy", "cpu", "large", "cavity",
+                                                        "split"}
     n = args.n
     log(f"geometry: {n}^3 sphere pack, 10% solid, seed 12345")
     flags = I.sphere_pack((n, n, n), 0.10, seed=12345)
@@ -390,6 +392,13 @@ def main():
             res[st] = forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st, args.steps,
                                   args.warmup, s)
             log(f"  {res[st]['mlups']:.0f} MLUPS, {res[st]['alg_gbs']:.0f} GB/s algorithmic")
+    if "split" in legs:
+        # the paper's split design: a separate obstacle kernel before each step
+        log("split design (separate obstacle kernel), f32 and f16")
+        res["split"] = [forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st, args.steps,
+                                    args.warmup, s, obstacle_kernel=1)
+                        for st, s in (("f32", 0), ("f16", 12))]
+        log("  " + ", ".join(f"{c['mlups']:.0f}" for c in res["split"]) + " MLUPS")
     if "cavity" in legs:
         log(f"lid-driven cavity {n}^3, f32 and f16")
         res["cavity"] = [cavity_leg(torch, "f32", n, args.steps, args.warmup),
@@ -447,6 +456,8 @@ def main():
         line["large"] = res["large"]
     if "cavity" in res:
         line["cavity"] = res["cavity"]
+    if "split" in res:
+        line["split_obstacle_kernel"] = res["split"]
     if "copy" in res:
         line["copy_gbs"] = res["copy"]["gbs"]
         if main_leg:

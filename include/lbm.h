@@ -118,7 +118,13 @@ typedef struct {
                              finite (tangential to the wall for a physical
                              moving wall); all 0 = every wall at rest */
   int32_t equilibrium;    /* lbm_equilibrium */
-  int32_t reserved;       /* must be 0 */
+  int32_t obstacle_kernel; /* 0: bounce-back fused into the pull through the
+                              solid markers (default); 1: the paper's split
+                              design (Sec. 7), a separate kernel writing the
+                              bounce-back values into the solid cells' slots
+                              of the source grid before each step (for the
+                              measured comparison; with it lbm_step_from
+                              rewrites the solid-cell slots of src) */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -169,7 +175,8 @@ lbm_status lbm_step(lbm_ctx* ctx, int32_t n);
 /* One step from an arbitrary grid `src` (state f*(t), same layout) into
  * `dst` (receives f*(t+1)); the context's own grids and time are untouched.
  * src and dst must differ.  Used to recompute forward states for the adjoint.
- * Errors: LBM_E_ARG, LBM_E_HIP. */
+ * With obstacle_kernel = 1 the solid-cell slots of src (which carry no state)
+ * are rewritten; its fluid values are not.  Errors: LBM_E_ARG, LBM_E_HIP. */
 lbm_status lbm_step_from(lbm_ctx* ctx, const void* src, void* dst);
 
 /* Macroscopic fields of the current time level t from the stored f*(t):

@@ -13,8 +13,12 @@ LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = ["kernels.hip", "abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+# -ffp-contract=on: multiply-adds are fused only inside one source
+# expression, as written, so every template instantiation of the collision
+# (wall kinds, split or fused bounce-back, cells per lane) rounds identically;
+# the default cross-statement fusion pairs products differently per kernel.
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fvisibility=hidden", "-Wall", "-Wno-unused-result",
     "-I" + os.path.join(ROOT, "include"),

@@ -65,7 +65,8 @@ lbm_status check_params(const lbm_params* p, Sizes* sz) {
     if (!std::isfinite(p->wall_u[d])) return fail(LBM_E_ARG, "wall_u[%d] is not finite", d);
   if (p->equilibrium != LBM_EQ_QIAN && p->equilibrium != LBM_EQ_INCOMPRESSIBLE)
     return fail(LBM_E_ARG, "unknown equilibrium %d", p->equilibrium);
-  if (p->reserved != 0) return fail(LBM_E_ARG, "reserved must be 0");
+  if (p->obstacle_kernel != 0 && p->obstacle_kernel != 1)
+    return fail(LBM_E_ARG, "obstacle_kernel must be 0 or 1 (got %d)", p->obstacle_kernel);
   if (p->storage == LBM_F16 && (p->f16_scale_log2 < -24 || p->f16_scale_log2 > 24))
     return fail(LBM_E_ARG, "f16_scale_log2 must be in [-24, 24] (got %d)", p->f16_scale_log2);
   if (p->x_align < 0 || p->x_align > 4096)
@@ -113,6 +114,12 @@ lbm_status check_ctx(const lbm_ctx* c) {
 }
 
 lbm_status launch_steps(lbm_ctx* c, const void* src, void* dst) {
+  if (c->flags && c->ph.split) {
+    // the split design: bounce-back values into the solid slots of src first
+    hipError_t e = lbm::launch_obstacle(c->p.storage, c->geo, c->ph, const_cast<void*>(src),
+                                        c->flags, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "obstacle kernel launch");
+  }
   hipError_t e = lbm::launch_step(c->p.storage, c->flags != nullptr, c->force, c->geo, c->ph, src,
                                   dst, c->flags, c->stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "stream-collide launch");
@@ -179,6 +186,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* grid_a, void* grid
   c->ph.moving =
       flags != nullptr && (p->wall_u[0] != 0.0 || p->wall_u[1] != 0.0 || p->wall_u[2] != 0.0);
   c->ph.incomp = p->equilibrium == LBM_EQ_INCOMPRESSIBLE;
+  c->ph.split = p->obstacle_kernel == 1;
   c->grid[0] = grid_a;
   c->grid[1] = grid_b;
   c->flags = flags;

@@ -32,6 +32,7 @@ struct PhysParams {
   double wall_u[3];  // velocity of the moving-wall cells
   bool moving;       // wall_u != 0 and the grid has flags: moving-wall markers are in use
   bool incomp;       // He-Luo incompressible equilibrium (u = j + F/2)
+  bool split;        // bounce-back by the separate obstacle kernel (the paper's split design)
 };
 
 Geo make_geo(int nx, int ny, int nz, int xs);
@@ -43,6 +44,8 @@ hipError_t launch_mark_solids(int storage, const Geo& g, const PhysParams& ph, v
                               const uint8_t* flags, hipStream_t s);
 hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
                        const void* src, void* dst, const uint8_t* flags, hipStream_t s);
+hipError_t launch_obstacle(int storage, const Geo& g, const PhysParams& ph, void* grid,
+                           const uint8_t* flags, hipStream_t s);
 hipError_t launch_macro(int storage, bool out_f64, const Geo& g, const PhysParams& ph,
                         const void* grid, const uint8_t* flags, void* rho, void* u, hipStream_t s);
 hipError_t launch_reduce(int storage, const Geo& g, const PhysParams& ph, const void* grid,

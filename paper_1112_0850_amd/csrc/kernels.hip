@@ -218,6 +218,7 @@ struct StepK {
   C Kq[9];       // (1 - omega/2) q (c.F) S (Guo, 9 W (c.u)(c.F) part)
   C Ka[9];       // (1 - omega/2) a (c.F) S (Guo, 3 W c.F part)
   C Kw[Q];       // 6 w_i (c_i.u_w) S      (moving-wall bounce-back term)
+  int moving;    // moving-wall markers in use (marker choice of WALLS = 3)
 };
 
 // BGK relaxation towards the Qian equilibrium with Guo forcing, in place, in
@@ -297,6 +298,10 @@ __device__ __forceinline__ void collide(C* f, const StepK<C>& k, C fon) {
 // well.  In the last case a moving-wall cell's marker is +infinity instead
 // of NaN, and a bounced-back value whose pull returned infinity gains the
 // wall term 6 w_i (c_i.u_w) -- the moving wall costs nothing away from it.
+// WALLS = 3 is the paper's split design (non-fluid cells treated in a
+// separate kernel, Sec. 7): k_obstacle has already written the bounce-back
+// values into the solid cells' slots of src, so the step pulls with no
+// marker test at all; flags still give the solid and no-force bits.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void stream_store(T* p, T v) {
@@ -327,6 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
   using T = typename Storage<K>::T;
   constexpr bool SCALED = (K == ST_F16);
   constexpr bool SOLIDS = WALLS != 0;
+  constexpr bool MARKERS = WALLS == 1 || WALLS == 2;
   // g describes 64*M-cell segments (step_geo); same block remap as locate().
   const int b = blockIdx.x;
   const int lb = (b < g.nb8) ? ((b & 7) * (g.nb8 >> 3) + (b >> 3)) : b;
@@ -361,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     solid[m] = SOLIDS && (fl[m] & FLAG_SOLID);
-    if (SOLIDS) {
+    if (MARKERS) {
 #pragma unroll
       for (int i = 1; i < Q; ++i)
         if (is_marker<WALLS>(f[m][i]) && !solid[m]) {
@@ -378,12 +384,42 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
       collide<C, FORCE, SCALED, INC>(f[m], k, (fl[m] & FLAG_NOFORCE) ? C(0) : C(1));
     else
       collide<C, FORCE, SCALED, INC>(f[m], k, C(1));
-    const C marker = solid_marker<C>(fl[m], WALLS == 2);
+    const C marker = solid_marker<C>(fl[m], WALLS == 2 || (WALLS == 3 && k.moving));
     if (valid[m]) {
 #pragma unroll
       for (int i = 0; i < Q; ++i)
         stream_store(elem(dst, pb, i, n[m].own), T(solid[m] ? marker : f[m][i]));
     }
+  }
+}
+
+// The separate obstacle kernel of the split design (WALLS = 3 steps): every
+// solid cell s writes, into its slot i, the value the fluid neighbour
+// x = s + c_i will pull along c_i: f*_opp(i)(x), plus the moving-wall term
+// for a moving wall.  Each written slot has exactly one writer and no
+// written slot is read by this kernel, so it runs in place on the source
+// grid of the following step.
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_obstacle(typename Storage<K>::T* __restrict__ grid,
+                                                     const uint8_t* __restrict__ flags, Geo g,
+                                                     Phys<typename Storage<K>::C> ph) {
+  using T = typename Storage<K>::T;
+  using C = typename Storage<K>::C;
+  const Loc l = locate(g);
+  if (!l.valid) return;
+  const Nbhd n = neighbourhood(g, l);
+  const uint8_t fl = flags[n.fown];
+  if (!(fl & FLAG_SOLID)) return;
+  const bool mv = ph.moving && (fl & FLAG_MOVING);
+  const size_t pb = size_t(g.plane) * sizeof(T);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int o = D3Q19::opp[i];
+    // s - c_o = s + c_i is the fluid neighbour that pulls slot i of s
+    if (flags[src_foff(n, o)] & FLAG_SOLID) continue;
+    C v = C(*elem(grid, pb, o, src_off(n, o)));
+    if (mv) v += ph.Kw[i] * ph.scale;
+    *elem(grid, pb, i, n.own) = T(v);
   }
 }
 
@@ -899,6 +935,7 @@ static StepK<C> make_stepk(const PhysParams& p) {
     k.Ka[q] = C(fpre * 3.0 * weight<double>(i) * cF * S);
   }
   for (int i = 0; i < Q; ++i) k.Kw[i] = C(wall_term(i, p.wall_u) * S);
+  k.moving = p.moving ? 1 : 0;
   return k;
 }
 
@@ -935,6 +972,7 @@ template <int K, bool INC>
 static void step_w(bool solids, bool force, const Geo& g, const PhysParams& ph, const void* src,
                    void* dst, const uint8_t* flags, hipStream_t s) {
   if (!solids) step_f<K, 0, INC>(force, g, ph, src, dst, flags, s);
+  else if (ph.split) step_f<K, 3, INC>(force, g, ph, src, dst, flags, s);
   else if (!ph.moving) step_f<K, 1, INC>(force, g, ph, src, dst, flags, s);
   else step_f<K, 2, INC>(force, g, ph, src, dst, flags, s);
 }
@@ -954,6 +992,28 @@ hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const
     case ST_BF16: step_k<ST_BF16>(solids, force, g, ph, src, dst, flags, s); break;
     case ST_F64: step_k<ST_F64>(solids, force, g, ph, src, dst, flags, s); break;
     case ST_F32X: step_k<ST_F32X>(solids, force, g, ph, src, dst, flags, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int K>
+static void obstacle_t(const Geo& g, const PhysParams& ph, void* grid, const uint8_t* flags,
+                       hipStream_t s) {
+  using S = Storage<K>;
+  hipLaunchKernelGGL(k_obstacle<K>, dim3(g.nblocks), dim3(kBlock), 0, s,
+                     reinterpret_cast<typename S::T*>(grid), flags, g,
+                     to_phys<typename S::C>(ph));
+}
+
+hipError_t launch_obstacle(int storage, const Geo& g, const PhysParams& ph, void* grid,
+                           const uint8_t* flags, hipStream_t s) {
+  switch (storage) {
+    case ST_F32: obstacle_t<ST_F32>(g, ph, grid, flags, s); break;
+    case ST_F16: obstacle_t<ST_F16>(g, ph, grid, flags, s); break;
+    case ST_BF16: obstacle_t<ST_BF16>(g, ph, grid, flags, s); break;
+    case ST_F64: obstacle_t<ST_F64>(g, ph, grid, flags, s); break;
+    case ST_F32X: obstacle_t<ST_F32X>(g, ph, grid, flags, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

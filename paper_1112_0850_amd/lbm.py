@@ -45,11 +45,13 @@ class LBM:
     solid flag bits).  ``storage`` in {'f32', 'f16', 'bf16', 'f64', 'f32x'}
     ('f32x': FP32 storage with FP64 collision arithmetic).  ``wall_u``: the
     velocity of the cells flagged solid + moving (bit 2); ``equilibrium``:
-    'qian' (u = j/rho) or 'incompressible' (He-Luo, u = j/rho0)."""
+    'qian' (u = j/rho) or 'incompressible' (He-Luo, u = j/rho0);
+    ``obstacle_kernel=1`` selects the split design (a separate bounce-back
+    kernel before each step) instead of the fused solid markers."""
 
     def __init__(self, shape, tau, force=(0.0, 0.0, 0.0), storage="f32", flags=None, u0=None,
                  rho0=None, f16_scale_log2=0, x_align=0, device="cuda", wall_u=(0.0, 0.0, 0.0),
-                 equilibrium="qian"):
+                 equilibrium="qian", obstacle_kernel=0):
         self.shape = tuple(int(s) for s in shape)
         if len(self.shape) != 3:
             raise ValueError("shape must be (nz, ny, nx)")
@@ -66,7 +68,7 @@ class LBM:
         self.equilibrium = EQUILIBRIUM[equilibrium] if isinstance(equilibrium, str) \
             else int(equilibrium)
         self.params = A.params(self.shape, tau, self.force, self.storage, f16_scale_log2, x_align,
-                               self.wall_u, self.equilibrium)
+                               self.wall_u, self.equilibrium, obstacle_kernel)
         xs, gb, sb, ab = A.lbm_query(self.params)
         self.x_stride, self.grid_bytes, self.adj_partials_bytes = xs, gb, ab
         nz, ny, nx = self.shape

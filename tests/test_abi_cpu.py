@@ -101,16 +101,18 @@ def test_invalid_params_rejected(kw, msg):
     assert msg in str(e.value)
 
 
-def test_params_layout_and_reserved_field():
-    # six int32, tau, force[3], wall_u[3], equilibrium, reserved: 88 bytes, no padding
+def test_params_layout_and_obstacle_field():
+    # six int32, tau, force[3], wall_u[3], equilibrium, obstacle_kernel: 88 bytes, no padding
     assert ctypes.sizeof(A.lbm_params) == 88
     assert A.lbm_params.wall_u.offset == 56 and A.lbm_params.equilibrium.offset == 80
     p = A.params((4, 4, 4), 0.6, wall_u=(0.1, 0, 0), equilibrium=A.LBM_EQ_INCOMPRESSIBLE)
     A.lbm_query(p)
-    p.reserved = 1
+    p.obstacle_kernel = 1
+    A.lbm_query(p)
+    p.obstacle_kernel = 2
     with pytest.raises(A.LBMError) as e:
         A.lbm_query(p)
-    assert e.value.status == A.LBM_E_ARG and "reserved" in str(e.value)
+    assert e.value.status == A.LBM_E_ARG and "obstacle_kernel" in str(e.value)
 
 
 def test_infinite_tau_accepted():
