@@ -20,6 +20,7 @@ struct Geo {
   int32_t nrows;    // ny * nz
   int32_t nblocks;  // blocks launched (4 segments each)
   int32_t nb8;      // nblocks rounded down to a multiple of 8
+  int32_t yb;       // step kernel: rows are visited in bands of yb rows of y, z fastest
 };
 
 constexpr int kBlock = 256;
