@@ -144,6 +144,28 @@ __device__ __forceinline__ uint32_t src_foff(const Nbhd& n, int i) {
   return n.frow[1 - D3Q19::cz[i]][1 - D3Q19::cy[i]] + n.xn[D3Q19::cx[i] + 1];
 }
 
+// The pull source of direction i split into its wave-uniform row offset and
+// its per-lane x (the step kernel's waves each own part of one row).
+__device__ __forceinline__ uint32_t src_row(const Nbhd& n, int i) {
+  return n.row[1 - D3Q19::cz[i]][1 - D3Q19::cy[i]];
+}
+__device__ __forceinline__ uint32_t src_x(const Nbhd& n, int i) { return n.xn[D3Q19::cx[i] + 1]; }
+
+// Element (i, row + x) with the row offset folded into the wave-uniform base,
+// so that each load is a scalar base plus one of three per-lane x offsets
+// (x - 1, x, x + 1) and needs no per-load vector address arithmetic.
+template <typename T>
+__device__ __forceinline__ T* elem_rx(T* grid, size_t plane_bytes, int i, uint32_t row, uint32_t x) {
+  char* b = reinterpret_cast<char*>(grid) + size_t(i) * plane_bytes + size_t(row) * sizeof(T);
+  return reinterpret_cast<T*>(b + x * uint32_t(sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ const T* elem_rx(const T* grid, size_t plane_bytes, int i, uint32_t row,
+                                            uint32_t x) {
+  const char* b = reinterpret_cast<const char*>(grid) + size_t(i) * plane_bytes + size_t(row) * sizeof(T);
+  return reinterpret_cast<const T*>(b + x * uint32_t(sizeof(T)));
+}
+
 // Population element (i, off): a wave-uniform base of direction array i plus
 // a 32-bit per-lane byte offset (one direction array is < 4 GiB), which maps
 // onto the scalar-base + 32-bit-offset form of global loads and stores and
@@ -374,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[m][i] = C(*elem(src, pb, i, src_off(n[m], i)));
+    for (int i = 0; i < Q; ++i) f[m][i] = C(*elem_rx(src, pb, i, src_row(n[m], i), src_x(n[m], i)));
   bool solid[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
@@ -383,7 +405,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 #pragma unroll
       for (int i = 1; i < Q; ++i)
         if (is_marker<WALLS>(f[m][i]) && !solid[m]) {
-          C b = C(*elem(src, pb, D3Q19::opp[i], n[m].own));
+          C b = C(*elem_rx(src, pb, D3Q19::opp[i], n[m].row[1][1], n[m].xn[1]));
           if (WALLS == 2 && __builtin_isinf(f[m][i])) b += k.Kw[i];
           f[m][i] = b;
         }
@@ -400,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
     if (valid[m]) {
 #pragma unroll
       for (int i = 0; i < Q; ++i)
-        stream_store(elem(dst, pb, i, n[m].own), T(solid[m] ? marker : f[m][i]));
+        stream_store(elem_rx(dst, pb, i, n[m].row[1][1], n[m].xn[1]), T(solid[m] ? marker : f[m][i]));
     }
   }
 }
