@@ -146,7 +146,8 @@ def sweep(torch):
     """MLUPS against the edge N of a periodic all-fluid cube (tau 0.6, no
     force, at rest), with the x-stride padded to 64 cells or not padded.
     Median of 5 timed repetitions per point; when N is a multiple of 64
-    both layouts are the same and the point is timed once."""
+    both layouts are the same and the point is timed once.  Up to N = 160
+    the padded layout is also timed with replayed graphs of 32 steps."""
     import statistics
     from paper_1112_0850_amd.lbm import LBM
     for st in ("f32", "f16", "f64"):
@@ -158,10 +159,15 @@ def sweep(torch):
                 steps = max(10, min(400, int(2e9 / n ** 3)))
                 ms = statistics.median(timed_steps(sim, torch, steps, max(3, steps // 10))
                                        for _ in range(5))
-                print(json.dumps({"sweep": st, "n": n, "padded": align == 0 or n % 64 == 0,
-                                  "x_stride": sim.x_stride, "same_layout": n % 64 == 0,
-                                  "ms_per_step": ms, "mlups": n ** 3 / ms / 1e3,
-                                  "grid_gb": 2 * sim.grid_bytes / 1e9}), flush=True)
+                rec = {"sweep": st, "n": n, "padded": align == 0 or n % 64 == 0,
+                       "x_stride": sim.x_stride, "same_layout": n % 64 == 0,
+                       "ms_per_step": ms, "mlups": n ** 3 / ms / 1e3,
+                       "grid_gb": 2 * sim.grid_bytes / 1e9}
+                if align == 0 and n <= 160:  # launch-bound sizes: replayed step graphs
+                    sim.use_graphs(32)
+                    msg = statistics.median(timed_steps(sim, torch, 320, 64) for _ in range(5))
+                    rec["graph_mlups"] = n ** 3 / msg / 1e3
+                print(json.dumps(rec), flush=True)
                 del sim
             torch.cuda.empty_cache()
     return 0

@@ -61,7 +61,8 @@
  *  - Every pointer is device memory owned by the caller, 256-byte aligned,
  *    and must stay valid while work that uses it is queued.  Calls enqueue
  *    on the context's stream and return without synchronising; nothing in
- *    this library allocates device memory.
+ *    this library allocates device memory (the optional step graphs of
+ *    lbm_use_graphs are the HIP runtime's).
  *  - Errors: every call returns lbm_status; LBM_OK = 0.  Invalid arguments
  *    are detected on the host before anything is enqueued (LBM_E_ARG) and
  *    leave the context unchanged.  lbm_last_error() gives a message for the
@@ -262,7 +263,18 @@ lbm_status lbm_adjoint_finish_dF(lbm_ctx* ctx, const double* dLdF_partials, doub
  * pointers 256-byte aligned, n_bytes a multiple of 16. */
 lbm_status lbm_stream_copy(void* c, const void* a, size_t n_bytes, void* stream);
 
-/* Destroys a context (host memory only; device memory stays the caller's). */
+/* Launch-bound runs (small grids): with steps_per_graph = G (even, 2..4096)
+ * lbm_step replays HIP graphs of G captured steps on the context's stream
+ * (one graph per starting grid, captured on first use on a library-owned
+ * stream; only the step kernels are recorded) and launches the remaining
+ * n mod G steps one by one; results are bit-identical to plain launches.
+ * 0 (the default) launches every step.  The HIP runtime owns the graphs'
+ * resources; changing G or destroying the context waits for the stream and
+ * releases them.  Errors: LBM_E_ARG, LBM_E_HIP. */
+lbm_status lbm_use_graphs(lbm_ctx* ctx, int32_t steps_per_graph);
+
+/* Destroys a context: its host memory and, if graphs were used, the graphs
+ * (after waiting for the context's stream); device memory stays the caller's. */
 void lbm_destroy(lbm_ctx* ctx);
 
 /* Message of the calling thread's latest error ("" if none). */

@@ -57,6 +57,7 @@ _SIGNATURES = {
     "lbm_adjoint_init": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_adjoint_finish_dF": (_st, [_vp, _vp, _vp]),
     "lbm_stream_copy": (_st, [_vp, _vp, C.c_size_t, _vp]),
+    "lbm_use_graphs": (_st, [_vp, C.c_int32]),
     "lbm_destroy": (None, [_vp]),
     "lbm_last_error": (C.c_char_p, []),
 }
@@ -197,6 +198,10 @@ def lbm_adjoint_finish_dF(ctx, partials, dLdF3):
 
 def lbm_stream_copy(dst, src, n_bytes, stream):
     check(lib().lbm_stream_copy(dst, src, int(n_bytes), stream))
+
+
+def lbm_use_graphs(ctx, steps_per_graph):
+    check(lib().lbm_use_graphs(ctx, int(steps_per_graph)))
 
 
 def lbm_destroy(ctx):

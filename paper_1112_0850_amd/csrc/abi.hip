@@ -104,6 +104,9 @@ struct lbm_ctx {
   int32_t cur;
   int64_t t;
   bool force;
+  int32_t graph_steps;         // 0: one launch per step; else replay graphs of this many steps
+  hipGraphExec_t graph[2];     // per starting grid, captured on first use
+  hipStream_t capture_stream;  // library-owned, used only to capture the graphs
 };
 
 namespace {
@@ -113,16 +116,61 @@ lbm_status check_ctx(const lbm_ctx* c) {
   return LBM_OK;
 }
 
-lbm_status launch_steps(lbm_ctx* c, const void* src, void* dst) {
+lbm_status launch_steps_on(lbm_ctx* c, const void* src, void* dst, hipStream_t s) {
   if (c->flags && c->ph.split) {
     // the split design: bounce-back values into the solid slots of src first
     hipError_t e = lbm::launch_obstacle(c->p.storage, c->geo, c->ph, const_cast<void*>(src),
-                                        c->flags, c->stream);
+                                        c->flags, s);
     if (e != hipSuccess) return hip_fail(e, "obstacle kernel launch");
   }
   hipError_t e = lbm::launch_step(c->p.storage, c->flags != nullptr, c->force, c->geo, c->ph, src,
-                                  dst, c->flags, c->stream);
+                                  dst, c->flags, s);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "stream-collide launch");
+}
+
+lbm_status launch_steps(lbm_ctx* c, const void* src, void* dst) {
+  return launch_steps_on(c, src, dst, c->stream);
+}
+
+void drop_graphs(lbm_ctx* c) {
+  for (int p = 0; p < 2; ++p)
+    if (c->graph[p]) {
+      (void)hipGraphExecDestroy(c->graph[p]);
+      c->graph[p] = nullptr;
+    }
+}
+
+// Captures graph_steps alternating steps starting from grid `parity` (an
+// even count, so the replay ends on the grid it started from).  Only kernel
+// launches are recorded.
+lbm_status build_graph(lbm_ctx* c, int parity) {
+  hipError_t e = hipSuccess;
+  if (!c->capture_stream) {
+    e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
+  }
+  e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "begin capture");
+  lbm_status st = LBM_OK;
+  int cur = parity;
+  for (int32_t k = 0; k < c->graph_steps && st == LBM_OK; ++k) {
+    st = launch_steps_on(c, c->grid[cur], c->grid[cur ^ 1], c->capture_stream);
+    cur ^= 1;
+  }
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(c->capture_stream, &g);
+  if (st != LBM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "end capture");
+  e = hipGraphInstantiate(&c->graph[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->graph[parity] = nullptr;
+    return hip_fail(e, "graph instantiation");
+  }
+  return LBM_OK;
 }
 
 }  // namespace
@@ -195,6 +243,9 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* grid_a, void* grid
   c->cur = 0;
   c->t = 0;
   c->force = p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0;
+  c->graph_steps = 0;
+  c->graph[0] = c->graph[1] = nullptr;
+  c->capture_stream = nullptr;
   hipError_t e = lbm::launch_fill_zero(grid_a, sz.grid_bytes, c->stream);
   if (e == hipSuccess) e = lbm::launch_fill_zero(grid_b, sz.grid_bytes, c->stream);
   if (e == hipSuccess)
@@ -211,6 +262,16 @@ lbm_status lbm_step(lbm_ctx* c, int32_t n) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
   if (n < 0) return fail(LBM_E_ARG, "step count must be >= 0 (got %d)", n);
+  while (c->graph_steps && n >= c->graph_steps) {
+    if (!c->graph[c->cur]) {
+      st = build_graph(c, c->cur);
+      if (st != LBM_OK) return st;
+    }
+    hipError_t e = hipGraphLaunch(c->graph[c->cur], c->stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    n -= c->graph_steps;
+    c->t += c->graph_steps;
+  }
   for (int32_t k = 0; k < n; ++k) {
     st = launch_steps(c, c->grid[c->cur], c->grid[c->cur ^ 1]);
     if (st != LBM_OK) return st;
@@ -363,7 +424,32 @@ lbm_status lbm_stream_copy(void* dst, const void* src, size_t n_bytes, void* str
   return e == hipSuccess ? LBM_OK : hip_fail(e, "copy launch");
 }
 
-void lbm_destroy(lbm_ctx* c) { delete c; }
+lbm_status lbm_use_graphs(lbm_ctx* c, int32_t steps_per_graph) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (steps_per_graph != 0 && (steps_per_graph < 2 || steps_per_graph > 4096 || steps_per_graph % 2))
+    return fail(LBM_E_ARG, "steps_per_graph must be 0 or an even count in [2, 4096] (got %d)",
+                steps_per_graph);
+  if (steps_per_graph != c->graph_steps) {
+    if (c->graph[0] || c->graph[1]) {
+      hipError_t e = hipStreamSynchronize(c->stream);  // no replay of the old graphs in flight
+      if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+    }
+    drop_graphs(c);
+    c->graph_steps = steps_per_graph;
+  }
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  if (c->graph[0] || c->graph[1]) {
+    (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+  }
+  if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+  delete c;
+}
 
 const char* lbm_last_error(void) { return g_err; }
 

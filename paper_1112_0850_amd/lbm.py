@@ -143,6 +143,12 @@ class LBM:
     def set_current(self, parity, t):
         A.lbm_set_current(self.ctx, parity, t)
 
+    def use_graphs(self, steps_per_graph):
+        """Replay HIP graphs of `steps_per_graph` (even) captured steps in
+        step() -- for launch-bound small grids; 0 turns it off."""
+        A.lbm_use_graphs(self.ctx, steps_per_graph)
+        return self
+
     def close(self):
         if getattr(self, "ctx", None):
             A.lbm_destroy(self.ctx)

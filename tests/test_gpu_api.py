@@ -103,3 +103,34 @@ def test_optional_outputs_and_padding():
     nx = sim.shape[2]
     for g in sim.grids:
         assert not sim.grid_view(g)[..., nx:].any()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_graph_replays_match_plain_launches(storage):
+    """lbm_use_graphs: every replay (interleaved with eager steps of odd
+    counts, so both starting grids get a graph, with macroscopics reads and
+    synchronisations in between) leaves the same bytes as launching every
+    step; changing and switching off the graph length keeps it so."""
+    say("graph replays vs plain launches", storage)
+    kw = dict(f16_scale_log2=10) if storage == "f16" else {}
+    g, e = _sim(storage, **kw).use_graphs(8), _sim(storage, **kw)
+    plan = [8, 3, 16, 5, 8, 24, 1, 8]
+    for n in plan:
+        g.step(n)
+        e.step(n)
+        rg, _ = g.macroscopics()
+        re, _ = e.macroscopics()
+        torch.cuda.synchronize()
+        assert g.t == e.t and g.current == e.current
+        assert torch.equal(_bytes(g), _bytes(e)), n
+        assert torch.equal(rg, re)
+    g.use_graphs(4)
+    g.step(12)
+    e.step(12)
+    assert torch.equal(_bytes(g), _bytes(e))
+    g.use_graphs(0)
+    g.step(9)
+    e.step(9)
+    assert torch.equal(_bytes(g), _bytes(e))
+    with pytest.raises(A.LBMError):
+        g.use_graphs(3)
