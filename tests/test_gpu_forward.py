@@ -271,3 +271,30 @@ def test_rest_state_is_bit_exact_fixed_point():
     for st in STORAGES:
         sim = LBM(shape, 0.55, (0, 0, 0), st, flags=flags).step(5)
         assert not np.abs(check_solids(sim, flags)).max()
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f64", 1e-12)])
+def test_degenerate_domains(storage, tol):
+    """A single periodic cell (every neighbour is itself), one-cell-thin
+    periodic slabs, a fluid cell enclosed by solid cells (every link bounces
+    back), and an all-solid box (nothing to update)."""
+    say("degenerate domains", storage)
+    rng = np.random.default_rng(12)
+    F = (2e-4, -1e-4, 5e-5)
+    for shape, flags in [((1, 1, 1), None), ((1, 1, 70), None), ((1, 5, 1), None),
+                         ((5, 5, 5), None), ((4, 5, 6), np.ones((4, 5, 6), np.uint8))]:
+        if shape == (5, 5, 5):
+            flags = np.ones(shape, np.uint8)
+            flags[2, 2, 2] = 0
+        u0 = 0.04 * (rng.random((3,) + shape) - 0.5)
+        if flags is not None:
+            u0[:, flags & 1 == 1] = 0
+        sim, f = _run_pair(shape, 0.7, F, storage, flags, u0, 15)
+        if flags is not None and (flags & 1).all():
+            check_solids(sim, flags)
+            assert not sim.reduce().cpu().numpy().any()
+            rho, u = sim.macroscopics()
+            assert not rho.any() and not u.any()
+            continue
+        e_rho, e_u, _ = _macro_errors(sim, f, F, flags)
+        assert e_rho <= tol and e_u <= tol, (shape, e_rho, e_u)

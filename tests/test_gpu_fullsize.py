@@ -45,7 +45,7 @@ def _fcrop(flags, z, y, x, r):
     return np.ascontiguousarray(flags[np.ix_(zi, yi, xi)])
 
 
-@pytest.mark.parametrize("storage,s", [("f32", 0), ("f16", 12), ("bf16", 0)])
+@pytest.mark.parametrize("storage,s", [("f32", 0), ("f16", 12), ("bf16", 0), ("f64", 0), ("f32x", 0)])
 def test_sampled_step_at_full_size(geometry, storage, s):
     flags, u0 = geometry
     say(f"full size {N}^3 porous, {storage}: sampled one-step parity")
@@ -77,32 +77,42 @@ def test_sampled_cavity_step_at_full_size(storage, s):
     _sampled_step(sim, flags, storage, s, cells, CAVITY_TAU, (0, 0, 0), (CAVITY_U, 0, 0))
 
 
-def _sampled_step(sim, flags, storage, s, cells, tau, F, wall_u):
-    """Three more steps, then one: each sampled fluid cell of the last step
-    against the oracle's step of its 3^3 neighbourhood."""
-    sim.step(3)
-    prev = sim.save()
+def _sampled_step(sim, flags, storage, s, cells, tau, F, wall_u, extra=3):
+    """`extra` more steps, then one: each sampled fluid cell of the last step
+    against the oracle's step of its 3^3 neighbourhood, read from the state
+    before that step (no copy of the grid is made, so this runs at sizes
+    where only the two lattices fit)."""
+    nz, ny, nx = sim.shape
+    sim.step(extra)
+    torch.cuda.synchronize()
+    pv = sim.populations()
+    scale = 2.0 ** s
+    crops = []
+    for c in cells:
+        z, rem = divmod(int(c), ny * nx)
+        y, x = divmod(rem, nx)
+        g = _crop(pv, z, y, x, 1, nz, ny, nx).double().cpu().numpy() / scale
+        crops.append((z, y, x, g, _fcrop(flags, z, y, x, 1)))
     sim.step(1)
     torch.cuda.synchronize()
-    pv, cv = sim.grid_view(prev), sim.populations()
-    scale = 2.0 ** s
+    cv = sim.populations()
     worst = 0.0
     gmax = 0.0
-    for c in cells:
-        z, rem = divmod(int(c), N * N)
-        y, x = divmod(rem, N)
-        g = _crop(pv, z, y, x, 1, N, N, N).double().cpu().numpy() / scale
-        fl = _fcrop(flags, z, y, x, 1)
+    for z, y, x, g, fl in crops:
         f = g + W[:, None, None, None]
         f[:, fl & 1 == 1] = 0
         ref = O.step(f, tau, F, fl, n=1, wall_u=wall_u)[:, 1, 1, 1] - W
         got = cv[:, z, y, x].double().cpu().numpy() / scale
-        if storage == "f32":
+        if storage in ("f32", "f32x"):
             err = np.abs(got - ref)
             bound = 1e-6 * np.abs(ref).max() + 1e-12
+        elif storage == "f64":
+            # the oracle rounds f = g + w (|f| ~ 1/3) through ~50 operations:
+            # an absolute floor of ~50 ulp(1)/2, beside the relative bound
+            err = np.abs(got - ref)
+            bound = 1e-13 * np.abs(ref).max() + 1e-14
         else:
-            dt = np.float16 if storage == "f16" else None
-            if dt is not None:
+            if storage == "f16":
                 ulp = np.spacing(np.abs(ref * scale).astype(np.float16)).astype(np.float64) / scale
             else:  # bfloat16: 8 significant bits
                 ulp = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(ref), 1e-38))) - 7)
@@ -112,8 +122,43 @@ def _sampled_step(sim, flags, storage, s, cells, tau, F, wall_u):
         gmax = max(gmax, float(np.abs(ref).max()))
         assert (err <= bound).all(), (storage, z, y, x, err.max(), bound)
     say(f"  worst excess error {worst:.2e} (offset scale {gmax:.2e})")
-    del sim, prev
+    del sim
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("storage,n", [("f32", 768), ("f64", 640)])
+def test_sampled_step_large_boxes(storage, n):
+    """The large-box workloads as timed (5% spheres r 4-12, seed 777,
+    tau 0.55, g_x 1e-6): 68.9 GB FP32 at 768^3, 79.7 GB FP64 at 640^3."""
+    say(f"large box {n}^3 {storage}: sampled one-step parity")
+    flags = I.sphere_pack((n, n, n), 0.05, seed=777)
+    u0 = I.shear_waves((n, n, n), seed=5, amplitude=0.02)
+    u0[:, flags & 1 == 1] = 0
+    sim = LBM((n, n, n), TAU, F, storage, flags=flags, u0=torch.from_numpy(u0))
+    del u0
+    rng = np.random.default_rng(768)
+    fluid = np.flatnonzero((flags & 1 == 0).ravel())
+    _sampled_step(sim, flags, storage, 0, rng.choice(fluid, size=128, replace=False), TAU, F, None)
+
+
+def test_sampled_step_at_maximum_size():
+    """The largest FP32 box the 32-bit lane offsets allow: 1023^3 (x stride
+    1024: one direction array is 4,286,582,784 bytes, just under 4 GiB), a
+    channel with walls at y = 0 and y = 1022; cells sampled near the far end
+    of the arrays, where the offsets are largest, and at random."""
+    n = 1023
+    say(f"maximum size {n}^3 f32: sampled one-step parity")
+    p = A.params((n, n, n), TAU, F)
+    xs, gb, _, _ = A.lbm_query(p)
+    assert xs == 1024 and 19 * n * n * xs * 4 <= gb and n * n * xs * 4 < 2 ** 32
+    flags = I.channel_flags((n, n, n))
+    sim = LBM((n, n, n), TAU, F, "f32", flags=flags)
+    rng = np.random.default_rng(1023)
+    zyx = [(n - 1, n - 2, n - 1), (n - 1, 1, 0), (n - 2, n - 2, n - 2), (0, 1, 0), (n // 2, n - 2, 5)]
+    zyx += [(int(z), int(y), int(x)) for z, y, x in
+            zip(rng.integers(0, n, 60), rng.integers(1, n - 1, 60), rng.integers(0, n, 60))]
+    cells = [(z * n + y) * n + x for z, y, x in zyx]
+    _sampled_step(sim, flags, "f32", 0, cells, TAU, F, None, extra=2)
 
 
 def test_sampled_adjoint_step_at_rollout_size():
