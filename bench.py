@@ -255,26 +255,50 @@ def adjoint_leg(torch, n=128, steps=400, k=20):
 
 def cpu_leg(flags_np, seconds):
     """The FP64 oracle (plain loops, OpenMP) on the 128^3 crop of the same
-    geometry, timed on this host: a bounded sample of about `seconds`."""
+    geometry, timed on this host: a bounded sample of about `seconds` on all
+    host threads, and a shorter one on one thread.  Also the host's STREAM
+    copy bandwidth and the oracle's fraction of the paper's CPU model (copy
+    bandwidth / 456 B per FP64 fluid update with write-allocate, Sec. 4)."""
     import numpy as np
     from oracle import oracle as O
     crop = np.ascontiguousarray(flags_np[:128, :128, :128])
     shape = crop.shape
-    f = O.init(shape, crop)
-    f = O.step(f, 0.55, (1e-6, 0, 0), crop, n=2)  # warm-up (threads, pages)
-    nsteps, dt = 0, 0.0
-    while dt < seconds:  # whole chunks of 5 steps until the time budget is spent
-        t0 = time.perf_counter()
-        f = O.step(f, 0.55, (1e-6, 0, 0), crop, n=5)
-        dt += time.perf_counter() - t0
-        nsteps += 5
     cells = int(np.prod(shape))
     fluid = int((crop & 1 == 0).sum())
-    return {"value": cells * nsteps / dt / 1e6, "unit": "MLUPS", "cores": O.threads(),
+
+    def timed(budget, chunk):
+        f = O.init(shape, crop)
+        f = O.step(f, 0.55, (1e-6, 0, 0), crop, n=1)  # warm-up (threads, pages)
+        nsteps, dt = 0, 0.0
+        while dt < budget:  # whole chunks of steps until the time budget is spent
+            t0 = time.perf_counter()
+            f = O.step(f, 0.55, (1e-6, 0, 0), crop, n=chunk)
+            dt += time.perf_counter() - t0
+            nsteps += chunk
+        return nsteps, dt
+
+    threads = O.threads()
+    nsteps, dt = timed(seconds, 5)
+    O.set_threads(1)
+    n1, dt1 = timed(seconds / 4, 1)
+    O.set_threads(threads)
+    copy = O.host_copy_gbs()
+    model_mflups = copy * 1e3 / 456
+    mflups = fluid * nsteps / dt / 1e6
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return {"value": cells * nsteps / dt / 1e6, "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"FP64 oracle, {nsteps} steps of the 128^3 crop of the porous geometry "
                       f"({fluid} fluid cells), {dt:.1f} s",
-            "mflups": fluid * nsteps / dt / 1e6, "host_copy_gbs": O.host_copy_gbs()}
+            "mflups": mflups, "one_thread_mlups": cells * n1 / dt1 / 1e6,
+            "one_thread_sample": f"{n1} steps, {dt1:.1f} s", "host_cpu": model,
+            "host_copy_gbs": copy, "model_mflups_456B": model_mflups,
+            "frac_of_model": mflups / model_mflups}
 
 
 def traffic_entry(alg_bytes, ms):
@@ -411,8 +435,9 @@ def main():
                          cavity_leg(torch, "f16", n, args.steps, args.warmup, 10)]
         log("  " + ", ".join(f"{c['mlups']:.0f}" for c in res["cavity"]) + " MLUPS")
     if "adjoint" in legs:
-        log("adjoint 128^3")
+        log("adjoint 128^3 and 256^3")
         res["adjoint"] = adjoint_leg(torch)
+        res["adjoint_256"] = adjoint_leg(torch, 256)
     if "large" in legs:
         del flags_t
         torch.cuda.empty_cache()
@@ -458,6 +483,7 @@ def main():
         line["f16_over_f32"] = res["f16"]["mlups"] / res["f32"]["mlups"]
     if "adjoint" in res:
         line["adjoint"] = res["adjoint"]
+        line["adjoint_256"] = res["adjoint_256"]
     if "large" in res:
         line["large"] = res["large"]
     if "cavity" in res:
@@ -468,6 +494,8 @@ def main():
         line["copy_gbs"] = res["copy"]["gbs"]
         if main_leg:
             line["frac_of_copy_bw"] = main_leg["alg_gbs"] / res["copy"]["gbs"]
+    line["device"] = torch.cuda.get_device_name(0)
+    line["hip_version"] = torch.version.hip
     line["context"] = "paper: 650 MLUPS SP / 290 MLUPS DP on an NVIDIA Tesla C2070 (other hardware)"
     print(json.dumps(line), flush=True)
     return 0

@@ -661,3 +661,12 @@ int oracle_threads(void) {
   return 1;
 #endif
 }
+
+/* Thread count of the following oracle calls (for the CPU timing). */
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  extern void omp_set_num_threads(int);
+  if (n >= 1) omp_set_num_threads(n);
+#endif
+  return oracle_threads();
+}

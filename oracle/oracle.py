@@ -47,6 +47,7 @@ def load(path):
         "oracle_adjoint_init": [i, i, i, u8p, i, dp, dp, dp, dp, dp],
         "oracle_host_copy": [dp, dp, l, i],
         "oracle_threads": [],
+        "oracle_set_threads": [i],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -239,6 +240,11 @@ def adjoint_init(lam0, u0, flags=None, rho0=None, incompressible=False):
 
 def threads():
     return int(lib().oracle_threads())
+
+
+def set_threads(n):
+    """Thread count of the following oracle calls; returns the count in use."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def host_copy_gbs(n=1 << 25, reps=5):
