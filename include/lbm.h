@@ -26,7 +26,11 @@
  *    (1,2) (3,4) (5,6) (7,8) (9,10) (11,12) (13,14) (15,16) (17,18).
  *  - Population grid ("grid"): structure of arrays [19][nz][ny][x_stride],
  *    x contiguous, x_stride >= nx from lbm_query (padding cells after each
- *    x-row, never computed -- the paper's Sec. 6 alignment padding).  Each
+ *    x-row, never computed -- the paper's Sec. 6 alignment padding); the 19
+ *    direction arrays start dir_stride elements apart (dir_stride = nz * ny *
+ *    x_stride + 256 bytes of padding, which keeps the arrays off power-of-two
+ *    distances from each other), so element (i, z, y, x) is at
+ *    i * dir_stride + (z * ny + y) * x_stride + x.  Each
  *    element of a fluid cell holds the OFFSET g_i = f_i - w_i of the
  *    post-collision population f*_i after the latest step, in the storage
  *    type:
@@ -132,13 +136,14 @@ typedef struct lbm_ctx lbm_ctx;
 
 /* Sizes the caller must allocate for `p` (any output pointer may be NULL):
  *   x_stride       padded x extent of a grid row, in cells;
+ *   dir_stride     elements from one direction array to the next;
  *   grid_bytes     bytes of ONE population grid (two are needed);
  *   scratch_bytes  bytes of the reduction scratch passed to lbm_init;
  *   adj_partials_bytes  bytes of the dL/dF partial-sum buffer of the adjoint.
  * Errors: LBM_E_ARG for invalid parameters, LBM_E_UNSUPPORTED when one
  * direction's array would exceed 4 GiB - 1 or a grid exceeds 2^31 cells. */
-lbm_status lbm_query(const lbm_params* p, int64_t* x_stride, size_t* grid_bytes,
-                     size_t* scratch_bytes, size_t* adj_partials_bytes);
+lbm_status lbm_query(const lbm_params* p, int64_t* x_stride, int64_t* dir_stride,
+                     size_t* grid_bytes, size_t* scratch_bytes, size_t* adj_partials_bytes);
 
 /* Algorithmic HBM bytes of one fluid-cell update for a storage type: 19 loads
  * + 19 stores of one population (Sec. 4 byte model: 152 for FP32, 304 for

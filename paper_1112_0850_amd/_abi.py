@@ -35,7 +35,8 @@ class LBMError(RuntimeError):
 _vp = C.c_void_p
 _st = C.c_int32
 _SIGNATURES = {
-    "lbm_query": (_st, [C.POINTER(lbm_params), C.POINTER(C.c_int64), C.POINTER(C.c_size_t),
+    "lbm_query": (_st, [C.POINTER(lbm_params), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                        C.POINTER(C.c_size_t),
                         C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "lbm_bytes_per_update": (C.c_int32, [C.c_int32]),
     "lbm_lattice": (None, [C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
@@ -108,9 +109,12 @@ def params(shape, tau, force=(0.0, 0.0, 0.0), storage=LBM_F32, f16_scale_log2=0,
 # -- thin wrappers with the C names ----------------------------------------
 
 def lbm_query(p):
-    xs, gb, sb, ab = C.c_int64(), C.c_size_t(), C.c_size_t(), C.c_size_t()
-    check(lib().lbm_query(C.byref(p), C.byref(xs), C.byref(gb), C.byref(sb), C.byref(ab)))
-    return xs.value, gb.value, sb.value, ab.value
+    """(x_stride, dir_stride, grid_bytes, scratch_bytes, adj_partials_bytes)."""
+    xs, ds = C.c_int64(), C.c_int64()
+    gb, sb, ab = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    check(lib().lbm_query(C.byref(p), C.byref(xs), C.byref(ds), C.byref(gb), C.byref(sb),
+                          C.byref(ab)))
+    return xs.value, ds.value, gb.value, sb.value, ab.value
 
 
 def lbm_bytes_per_update(storage):

@@ -15,7 +15,7 @@ namespace lbm {
 struct Geo {
   int32_t nx, ny, nz;
   int32_t xs;       // x stride of a population row, in cells
-  uint32_t plane;   // elements of one direction array: nz * ny * xs
+  uint32_t plane;   // elements from one direction array to the next (nz * ny * xs + padding)
   int32_t nseg;     // 64-cell segments per row
   int32_t nrows;    // ny * nz
   int32_t nblocks;  // blocks launched (4 segments each)
@@ -36,7 +36,7 @@ struct PhysParams {
   bool split;        // bounce-back by the separate obstacle kernel (the paper's split design)
 };
 
-Geo make_geo(int nx, int ny, int nz, int xs);
+Geo make_geo(int nx, int ny, int nz, int xs, uint64_t dir_stride);
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_init(int storage, const Geo& g, const PhysParams& ph, void* grid,

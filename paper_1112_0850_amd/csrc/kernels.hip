@@ -28,13 +28,13 @@
 
 namespace lbm {
 
-Geo make_geo(int nx, int ny, int nz, int xs) {
+Geo make_geo(int nx, int ny, int nz, int xs, uint64_t dir_stride) {
   Geo g;
   g.nx = nx;
   g.ny = ny;
   g.nz = nz;
   g.xs = xs;
-  g.plane = uint32_t(uint64_t(nz) * uint64_t(ny) * uint64_t(xs));
+  g.plane = uint32_t(dir_stride);
   g.nseg = (nx + 63) / 64;
   g.nrows = ny * nz;
   const int64_t segs = int64_t(g.nseg) * g.nrows;

@@ -69,8 +69,9 @@ class LBM:
             else int(equilibrium)
         self.params = A.params(self.shape, tau, self.force, self.storage, f16_scale_log2, x_align,
                                self.wall_u, self.equilibrium, obstacle_kernel)
-        xs, gb, sb, ab = A.lbm_query(self.params)
-        self.x_stride, self.grid_bytes, self.adj_partials_bytes = xs, gb, ab
+        xs, ds, gb, sb, ab = A.lbm_query(self.params)
+        self.x_stride, self.dir_stride = xs, ds
+        self.grid_bytes, self.adj_partials_bytes = gb, ab
         nz, ny, nx = self.shape
         self.flags = _as_field(flags, self.shape, torch.uint8, self.device, "flags")
         self.rho0 = _as_field(rho0, self.shape, torch.float32, self.device, "rho0")
@@ -92,11 +93,14 @@ class LBM:
     def current(self):
         return A.lbm_current(self.ctx)
 
-    def grid_view(self, raw):
-        """A raw grid buffer viewed as [19, nz, ny, x_stride] of the storage dtype."""
+    def grid_view(self, buf, dtype=None):
+        """A grid-layout buffer viewed as [19, nz, ny, x_stride] (the direction
+        arrays dir_stride elements apart): a raw byte buffer in the storage
+        dtype (or `dtype`), or a typed buffer (e.g. an FP32 adjoint grid) as is."""
         nz, ny, _ = self.shape
-        n = 19 * nz * ny * self.x_stride
-        return raw.view(self.dtype)[:n].view(19, nz, ny, self.x_stride)
+        t = buf.view(dtype or self.dtype) if buf.dtype == torch.uint8 else buf
+        xs = self.x_stride
+        return torch.as_strided(t, (19, nz, ny, xs), (self.dir_stride, ny * xs, xs, 1))
 
     def populations(self):
         """View of the current grid: offsets g = f* - w (FP16: 2^s g)."""

@@ -64,11 +64,12 @@ def test_byte_model_matches_paper():
     ((512, 512, 512), A.LBM_F16, 0, 512), ((2, 2, 100), A.LBM_BF16, 16, 112)])
 def test_query_sizes(shape, storage, align, xs):
     p = A.params(shape, 0.6, storage=storage, x_align=align)
-    x_stride, gb, sb, ab = A.lbm_query(p)
+    x_stride, ds, gb, sb, ab = A.lbm_query(p)
     es = {A.LBM_F32: 4, A.LBM_F64: 8, A.LBM_F16: 2, A.LBM_BF16: 2}[storage]
     nz, ny, nx = shape
     assert x_stride == xs
-    assert gb >= 19 * nz * ny * xs * es and gb % 256 == 0 and gb - 19 * nz * ny * xs * es < 256
+    assert ds == nz * ny * xs + 256 // es  # 256 bytes between direction arrays
+    assert gb >= 19 * ds * es and gb % 256 == 0 and gb - 19 * ds * es < 256
     assert sb == 1024 * 5 * 8
     nblocks = -(-(-(-nx // 64) * ny * nz) // 4)
     assert ab == nblocks * 3 * 8

@@ -27,14 +27,14 @@ def _to_lam_grid(sim, lam):
     """float64 [19, nz, ny, nx] -> zero-padded FP32 buffer in the grid layout."""
     nz, ny, nx = sim.shape
     buf = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
-    v = buf[:19 * nz * ny * sim.x_stride].view(19, nz, ny, sim.x_stride)
+    v = sim.grid_view(buf)
     v[..., :nx].copy_(torch.from_numpy(lam).float())
     return buf
 
 
 def _from_lam_grid(sim, buf):
     nz, ny, nx = sim.shape
-    v = buf[:19 * nz * ny * sim.x_stride].view(19, nz, ny, sim.x_stride)
+    v = sim.grid_view(buf)
     return v[..., :nx].double().cpu().numpy()
 
 

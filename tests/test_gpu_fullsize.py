@@ -149,8 +149,8 @@ def test_sampled_step_at_maximum_size():
     n = 1023
     say(f"maximum size {n}^3 f32: sampled one-step parity")
     p = A.params((n, n, n), TAU, F)
-    xs, gb, _, _ = A.lbm_query(p)
-    assert xs == 1024 and 19 * n * n * xs * 4 <= gb and n * n * xs * 4 < 2 ** 32
+    xs, ds, gb, _, _ = A.lbm_query(p)
+    assert xs == 1024 and ds == n * n * xs + 64 and 19 * ds * 4 <= gb and n * n * xs * 4 < 2 ** 32
     flags = I.channel_flags((n, n, n))
     sim = LBM((n, n, n), TAU, F, "f32", flags=flags)
     rng = np.random.default_rng(1023)
@@ -169,14 +169,14 @@ def test_sampled_adjoint_step_at_rollout_size():
     sim.step(5)
     rng = np.random.default_rng(6)
     lam1 = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
-    v1 = lam1[:19 * n * n * sim.x_stride].view(19, n, n, sim.x_stride)
+    v1 = sim.grid_view(lam1)
     v1[..., :n].copy_(torch.from_numpy(rng.standard_normal((19, n, n, n)).astype(np.float32)))
     lam0 = torch.zeros_like(lam1)
     part = torch.zeros(sim.adj_partials_bytes // 8, dtype=torch.float64, device="cuda")
     P = lambda t: ctypes.c_void_p(t.data_ptr())
     A.lbm_adjoint_step(sim.ctx, P(sim.grids[sim.current]), P(lam1), P(lam0), P(part))
     torch.cuda.synchronize()
-    v0 = lam0[:19 * n * n * sim.x_stride].view(19, n, n, sim.x_stride)
+    v0 = sim.grid_view(lam0)
     fv = sim.populations()
     worst = 0.0
     for _ in range(64):
