@@ -16,6 +16,7 @@ in HBM before the timed region starts.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -25,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_1112_0850_amd", "csrc", "kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1112_0850_amd", "csrc", f)
+               for f in ("kernels.hip", "kernels.h", "d3q19.h", "abi.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_porous512_f32.json")
 
 
@@ -301,14 +303,26 @@ def cpu_leg(flags_np, seconds):
             "frac_of_model": mflups / model_mflups}
 
 
+def code_hash():
+    """SHA-256 of the library's device and ABI code with comments and
+    whitespace removed: the measured traffic stays attached to the code it
+    was taken on, and a comment edit does not detach it."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        text = open(path).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()
+
+
 def traffic_entry(alg_bytes, ms):
     """HBM traffic per launch from the committed rocprofv3 counter summary,
     or None when the kernel source changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     t = json.load(open(TRAFFIC_FILE))
-    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if t.get("kernels_sha256") != src_hash:
+    if t.get("code_sha256") != code_hash():
         return None
     return t.get("traffic_bytes_per_launch")
 
@@ -374,8 +388,7 @@ def profile_summary(trace_dir, fetch_dir, write_dir, n=512):
             row += ["", "", "", ""]
         if float(r["Percentage"]) > 0.05 or key:
             lines.append("| " + " | ".join(row) + " |")
-    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    out = {"kernels_sha256": src_hash, "fetch_scale": scale["FETCH_SIZE"],
+    out = {"code_sha256": code_hash(), "fetch_scale": scale["FETCH_SIZE"],
            "write_scale": scale["WRITE_SIZE"], "kernels": record}
     if "f32" in record:
         out["traffic_bytes_per_launch"] = record["f32"]["fetch_bytes"] + record["f32"]["write_bytes"]

@@ -363,10 +363,12 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
   const int seg = lb * 4 + wave;
   const int row = seg / g.nseg;
   if (row >= g.nrows) return;
-  // Rows in bands of yb rows of y, z running fastest inside a band: the
-  // rows z - 1 and z + 1 of a row are then processed a few blocks apart, so a
-  // bounce-back reload of f*_opp(i)(x) finds in L2 the line that the solid
-  // neighbour's lane pulled (or brings it in for that lane).
+  // Rows are visited in bands of yb consecutive y; inside a band y runs
+  // fastest, then z.  The rows y - 1 and y + 1 of a row are then processed
+  // by neighbouring waves and the rows z - 1 and z + 1 yb rows (a few dozen
+  // blocks) away, so a bounce-back reload of f*_opp(i)(x) finds in L2 the
+  // line that the solid neighbour's lane pulled (or brings it in for that
+  // lane).
   Loc l;
   {
     const int per_band = g.nz * g.yb;
