@@ -19,6 +19,7 @@ import hashlib
 import re
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -303,6 +304,18 @@ def cpu_leg(flags_np, seconds):
             "frac_of_model": mflups / model_mflups}
 
 
+def gpu_clocks():
+    """Current shader and memory clocks of card 0 from rocm-smi, read after
+    the timed legs; None where the tool or its output is unavailable."""
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
+                           text=True, timeout=30)
+        card = next(iter(json.loads(r.stdout).values()))
+        return {k.rstrip(":"): v for k, v in card.items() if "clock speed" in k} or None
+    except Exception:
+        return None
+
+
 def code_hash():
     """SHA-256 of the library's device and ABI code with comments and
     whitespace removed: the measured traffic stays attached to the code it
@@ -507,8 +520,11 @@ def main():
         line["copy_gbs"] = res["copy"]["gbs"]
         if main_leg:
             line["frac_of_copy_bw"] = main_leg["alg_gbs"] / res["copy"]["gbs"]
-    line["device"] = torch.cuda.get_device_name(0)
+    props = torch.cuda.get_device_properties(0)
+    line["device"] = f"{props.name} ({getattr(props, 'gcnArchName', '?')}, "\
+                     f"{props.multi_processor_count} CUs, {props.total_memory / 2**30:.0f} GiB)"
     line["hip_version"] = torch.version.hip
+    line["clocks"] = gpu_clocks()
     line["context"] = "paper: 650 MLUPS SP / 290 MLUPS DP on an NVIDIA Tesla C2070 (other hardware)"
     print(json.dumps(line), flush=True)
     return 0

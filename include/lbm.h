@@ -227,9 +227,9 @@ lbm_status lbm_restore(lbm_ctx* ctx, const void* src, int64_t t);
  * macroscopic fields (FP32 adjoint arithmetic), with either equilibrium and
  * with moving walls (the wall velocity is a constant of the map, so it
  * enters the recomputed state but not the transpose; no gradient is formed
- * for it).  lambda^n = dL/d f*(n) is FP32 in the grid layout
- * ([19][nz][ny][x_stride] floats); its solid-cell and padding slots must be
- * zero when first used (the seed writes zeros there and the step never
+ * for it).  lambda^n = dL/d f*(n) is FP32 in the grid layout (grid_bytes
+ * of floats, direction arrays dir_stride apart); its solid-cell and padding
+ * slots must be zero when first used (the seed writes zeros there and the step never
  * writes them).  dL/dF is accumulated per thread block in an FP64 partials
  * buffer (adj_partials_bytes) without atomics; lbm_adjoint_finish_dF reduces
  * it in a fixed order.  Errors: LBM_E_UNSUPPORTED for other storage types,
