@@ -21,6 +21,7 @@ import json
 import os
 import subprocess
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -39,8 +40,12 @@ def log(*a):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=980,
+                    help="timed steps of the headline legs (FP32, FP16, BF16); with the warm-up "
+                         "they make the 1000 steps of the porous workload")
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--aux-steps", type=int, default=200,
+                    help="timed steps of the other legs (at most --steps)")
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic porous box")
     ap.add_argument("--only", default="",
                     help="comma list of legs: f32,f16,bf16,f64,f32x,adjoint,copy,cpu,large,cavity,"
@@ -56,30 +61,44 @@ def parse():
     return ap.parse_args()
 
 
-def timed_steps(sim, torch, steps, warmup):
+def timed_steps(sim, torch, steps, warmup, clocks=None):
     """Average ms per fused step over `steps` launches, HIP events on the
-    solver's stream, bracketed by device synchronisation."""
+    solver's stream, bracketed by device synchronisation.  With a dict
+    `clocks`, a timer thread reads the GPU clocks (rocm-smi, a sysfs query
+    that starts no GPU work) 0.5 s into the timed steps."""
     sim.step(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    timer = None
+    if clocks is not None:
+        timer = threading.Timer(0.5, lambda: clocks.update(gpu_clocks() or {}))
     e0.record(sim.stream)
+    if timer:
+        timer.start()
     sim.step(steps)
     e1.record(sim.stream)
     torch.cuda.synchronize()
+    if timer:
+        timer.join()
     return e0.elapsed_time(e1) / steps
 
 
-def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s=0, **kw):
+def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s=0,
+                fields=None, clocks=None, **kw):
+    """Times `steps` steps after `warmup`; with a dict `fields`, stores the
+    final (rho, u) there (FP64, on the GPU) for the cross-storage comparison."""
     from paper_1112_0850_amd import _abi as A
     n = round(n_cells ** (1 / 3))
     sim = LBM((n, n, n), 0.55, (1e-6, 0.0, 0.0), storage, flags=flags_t, f16_scale_log2=s, **kw)
-    ms = timed_steps(sim, torch, steps, warmup)
+    ms = timed_steps(sim, torch, steps, warmup, clocks)
     r = sim.reduce().cpu().numpy()
+    if fields is not None:
+        fields[storage] = sim.macroscopics(f64=True)
     bpu = A.lbm_bytes_per_update(sim.storage)
     alg_bytes = bpu * n_fluid + n_cells  # populations of fluid cells + one flag byte per cell
     out = {
-        "storage": storage, "ms_per_step": ms,
+        "storage": storage, "timed_steps": steps, "ms_per_step": ms,
         "mlups": n_cells / ms / 1e3, "mflups": n_fluid / ms / 1e3,
         "bytes_per_update": bpu, "alg_bytes_per_step": alg_bytes,
         "alg_gbs": alg_bytes / ms / 1e6, "hbm_frac": alg_bytes / ms / 1e6 / HBM_PEAK_GBS,
@@ -131,7 +150,8 @@ def cavity_leg(torch, storage, n, steps, warmup, s=0):
     n_fluid = (n - 2) ** 3
     alg = A.lbm_bytes_per_update(sim.storage) * n_fluid + n ** 3
     out = {"workload": f"{n}^3 lid-driven cavity, lid (0.05, 0, 0), tau 0.55, {storage}",
-           "ms_per_step": ms, "mlups": n ** 3 / ms / 1e3, "mflups": n_fluid / ms / 1e3,
+           "timed_steps": steps, "ms_per_step": ms, "mlups": n ** 3 / ms / 1e3,
+           "mflups": n_fluid / ms / 1e3,
            "alg_gbs": alg / ms / 1e6, "hbm_frac": alg / ms / 1e6 / HBM_PEAK_GBS,
            "mass_drift_rel": abs(m1 - m0) / m0}
     if storage == "f16":
@@ -442,23 +462,44 @@ def main():
     if "copy" in legs:
         log("copy probe")
         res["copy"] = copy_leg(torch)
+    aux = min(args.aux_steps, args.steps)
+    fields, clocks = {}, {}
     for st, s in (("f32", 0), ("f16", 12), ("bf16", 0), ("f64", 0), ("f32x", 0)):
         if st in legs:
             log(f"forward {st}")
-            res[st] = forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st, args.steps,
-                                  args.warmup, s)
+            head = st in ("f32", "f16", "bf16")
+            res[st] = forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st,
+                                  args.steps if head else aux, args.warmup, s,
+                                  fields=fields if head else None,
+                                  clocks=clocks if st == "f32" else None)
             log(f"  {res[st]['mlups']:.0f} MLUPS, {res[st]['alg_gbs']:.0f} GB/s algorithmic")
+    if "f32" in fields:
+        # 16-bit storage against FP32 storage on the full box at the same step
+        fluid = (flags_t & 1) == 0
+        rho32, u32 = fields["f32"]
+        for st in ("f16", "bf16"):
+            if st in fields:
+                rho, u = fields[st]
+                res[f"{st}_vs_f32"] = {
+                    "steps": args.steps + args.warmup,
+                    "u_rel_linf": float((u - u32)[:, fluid].abs().max() / u32[:, fluid].abs().max()),
+                    "rho_rel_linf": float((rho - rho32)[fluid].abs().max() / rho32[fluid].abs().max()),
+                    "drho_rel_linf": float((rho - rho32)[fluid].abs().max()
+                                           / (rho32 - 1)[fluid].abs().max())}
+        del fluid, rho32, u32
+    fields.clear()
+    torch.cuda.empty_cache()
     if "split" in legs:
         # the paper's split design: a separate obstacle kernel before each step
         log("split design (separate obstacle kernel), f32 and f16")
-        res["split"] = [forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st, args.steps,
+        res["split"] = [forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st, aux,
                                     args.warmup, s, obstacle_kernel=1)
                         for st, s in (("f32", 0), ("f16", 12))]
         log("  " + ", ".join(f"{c['mlups']:.0f}" for c in res["split"]) + " MLUPS")
     if "cavity" in legs:
         log(f"lid-driven cavity {n}^3, f32 and f16")
-        res["cavity"] = [cavity_leg(torch, "f32", n, args.steps, args.warmup),
-                         cavity_leg(torch, "f16", n, args.steps, args.warmup, 10)]
+        res["cavity"] = [cavity_leg(torch, "f32", n, aux, args.warmup),
+                         cavity_leg(torch, "f16", n, aux, args.warmup, 10)]
         log("  " + ", ".join(f"{c['mlups']:.0f}" for c in res["cavity"]) + " MLUPS")
     if "adjoint" in legs:
         log("adjoint 128^3 and 256^3")
@@ -488,6 +529,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"D3Q19 BGK porous periodic box {n}^3, 10% solid random spheres "
                                f"r 4-12 (seed 12345), tau 0.55, g_x 1e-6, from rest, "
+                               f"{args.warmup + args.steps} steps ({args.steps} timed), "
                                f"{main_leg['storage'] if main_leg else ''} offset storage",
                    "cells": n_cells, "fluid_cells": n_fluid},
     }
@@ -505,6 +547,8 @@ def main():
     for st in ("f16", "bf16", "f64", "f32x"):
         if st in res:
             line[f"{st}_storage"] = res[st]
+            if f"{st}_vs_f32" in res:
+                line[f"{st}_storage"]["vs_f32_same_step"] = res[f"{st}_vs_f32"]
     if "f16" in res and "f32" in res:
         line["f16_over_f32"] = res["f16"]["mlups"] / res["f32"]["mlups"]
     if "adjoint" in res:
@@ -524,7 +568,7 @@ def main():
     line["device"] = f"{props.name} ({getattr(props, 'gcnArchName', '?')}, "\
                      f"{props.multi_processor_count} CUs, {props.total_memory / 2**30:.0f} GiB)"
     line["hip_version"] = torch.version.hip
-    line["clocks"] = gpu_clocks()
+    line["clocks_during_f32_leg"] = clocks or None
     line["context"] = "paper: 650 MLUPS SP / 290 MLUPS DP on an NVIDIA Tesla C2070 (other hardware)"
     print(json.dumps(line), flush=True)
     return 0

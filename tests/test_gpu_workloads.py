@@ -3,7 +3,7 @@
 analytic start-up series after 5000 steps; the exact discrete steady
 Poiseuille profile of BGK + half-way bounce-back + Guo forcing; and the
 porous 128^3 crop of the 512^3 geometry against the FP64 oracle in every
-storage (FP32 to 1e-5; the 16-bit errors are stated)."""
+storage over 1000 steps (FP32 to 1e-5; the 16-bit errors are stated)."""
 import math
 
 import numpy as np
@@ -71,22 +71,32 @@ def test_poiseuille_exact_steady_state_gpu(storage, tol):
 
 def test_porous_crop_errors_all_storages():
     """128^3 crop of the 512^3 bench geometry, tau = 0.55, g_x = 1e-6, from
-    rest, 200 steps, against the FP64 oracle."""
-    steps, tau, F = 200, 0.55, (1e-6, 0.0, 0.0)
+    rest, 1000 steps, against the FP64 oracle (errors every 200 steps).
+    FP32 and F32X within 1e-5 on rho and u (observed 8.8e-6 and 7e-8 for u at
+    step 1000; the FP32 error grows with the flow); FP16 and BF16 errors are
+    stated, with bounds of about three times the observed values as a guard
+    against regressions."""
+    steps, chunk, tau, F = 1000, 200, 0.55, (1e-6, 0.0, 0.0)
     flags = np.ascontiguousarray(I.sphere_pack((512, 512, 512), 0.10, seed=12345)[:128, :128, :128])
     shape = flags.shape
-    say("porous 128^3 crop, oracle", steps, "steps")
-    f = O.step(O.init(shape, flags), tau, F, flags, n=steps)
-    rho_r, u_r = O.macroscopics(f, F, flags)
-    m_r = O.reduce(f, F, flags)
     fl = (flags & 1) == 0
-    for st, s, tol in (("f32", 0, 1e-5), ("f32x", 0, 1e-5), ("f16", 12, 5e-2), ("bf16", 0, 5e-1)):
-        sim = LBM(shape, tau, F, st, flags=flags, f16_scale_log2=s).step(steps)
-        rho, u = sim.macroscopics(f64=True)
-        m = sim.reduce().cpu().numpy()
-        e_rho = rel_linf(rho.cpu().numpy(), rho_r, fl)
-        e_drho = float(np.abs(rho.cpu().numpy() - rho_r)[fl].max() / np.abs(rho_r - 1)[fl].max())
-        e_u = rel_linf(u.cpu().numpy(), u_r, fl)
-        say(f"  {st}: rel L-inf rho {e_rho:.2e}  delta-rho {e_drho:.2e}  u {e_u:.2e}  "
-            f"mass drift {abs(m[0] - m_r[0]) / m_r[0]:.2e}")
-        assert e_u <= tol and e_rho <= max(tol, 1e-5)
+    bars = {"f32": 1e-5, "f32x": 1e-5, "f16": 2e-3, "bf16": 2e-2}
+    sims = {st: LBM(shape, tau, F, st, flags=flags, f16_scale_log2=s)
+            for st, s in (("f32", 0), ("f32x", 0), ("f16", 12), ("bf16", 0))}
+    f = O.init(shape, flags)
+    m0 = O.reduce(f, F, flags)[0]
+    for t in range(chunk, steps + 1, chunk):
+        f = O.step(f, tau, F, flags, n=chunk)
+        rho_r, u_r = O.macroscopics(f, F, flags)
+        say(f"porous 128^3 crop, step {t}: oracle max|u| {np.abs(u_r).max():.3e}")
+        for st, sim in sims.items():
+            sim.step(chunk)
+            rho, u = sim.macroscopics(f64=True)
+            rho, u = rho.cpu().numpy(), u.cpu().numpy()
+            m = sim.reduce().cpu().numpy()
+            e_rho = rel_linf(rho, rho_r, fl)
+            e_drho = float(np.abs(rho - rho_r)[fl].max() / np.abs(rho_r - 1)[fl].max())
+            e_u = rel_linf(u, u_r, fl)
+            say(f"  {st}: rel L-inf rho {e_rho:.2e}  delta-rho {e_drho:.2e}  u {e_u:.2e}  "
+                f"mass drift {abs(m[0] - m0) / m0:.2e}")
+            assert e_u <= bars[st] and e_rho <= max(bars[st], 1e-5), (st, t)
