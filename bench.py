@@ -15,11 +15,11 @@ Output: one JSON line on stdout.  Inputs are synthetic and seeded, resident
 in HBM before the timed region starts.
 """
 import argparse
+import glob
 import hashlib
 import re
 import json
 import os
-import subprocess
 import sys
 import threading
 import time
@@ -64,8 +64,8 @@ def parse():
 def timed_steps(sim, torch, steps, warmup, clocks=None):
     """Average ms per fused step over `steps` launches, HIP events on the
     solver's stream, bracketed by device synchronisation.  With a dict
-    `clocks`, a timer thread reads the GPU clocks (rocm-smi, a sysfs query
-    that starts no GPU work) 0.5 s into the timed steps."""
+    `clocks`, a timer thread reads the GPU clocks (sysfs) 0.5 s into the
+    timed steps."""
     sim.step(warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -325,15 +325,22 @@ def cpu_leg(flags_np, seconds):
 
 
 def gpu_clocks():
-    """Current shader and memory clocks of card 0 from rocm-smi, read after
-    the timed legs; None where the tool or its output is unavailable."""
-    try:
-        r = subprocess.run(["rocm-smi", "--showclocks", "--json"], capture_output=True,
-                           text=True, timeout=30)
-        card = next(iter(json.loads(r.stdout).values()))
-        return {k.rstrip(":"): v for k, v in card.items() if "clock speed" in k} or None
-    except Exception:
-        return None
+    """Current shader and memory clocks from the driver's DPM tables in sysfs
+    (the level marked '*' of pp_dpm_sclk / pp_dpm_mclk of the first card that
+    has them); a plain file read, no child process.  None where unavailable."""
+    for dev in sorted(glob.glob("/sys/class/drm/card[0-9]*/device")):
+        out = {}
+        for name in ("pp_dpm_sclk", "pp_dpm_mclk", "pp_dpm_fclk"):
+            try:
+                with open(os.path.join(dev, name)) as fh:
+                    cur = [ln.split(":", 1)[1].strip(" *\n") for ln in fh if ln.rstrip().endswith("*")]
+            except (OSError, IndexError):
+                continue
+            if cur:
+                out[name[7:]] = cur[0]
+        if out:
+            return out
+    return None
 
 
 def code_hash():

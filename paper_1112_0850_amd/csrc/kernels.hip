@@ -192,12 +192,23 @@ __device__ __forceinline__ C cdot(int i, C x, C y, C z) {
   return r;
 }
 
+// delta_rho = sum of the offsets, summed over opposite pairs first.  An
+// offset is dominated by its first-order part w_i 3 c_i.u, which cancels in
+// g_i + g_opp(i) (exactly when the two have opposite signs and are within a
+// factor of two of each other), so the partial sums stay at the scale of
+// delta_rho instead of that of the offsets.
+template <typename C>
+__device__ __forceinline__ C delta_rho(const C* f) {
+  const C s1 = f[1] + f[2], s3 = f[3] + f[4], s5 = f[5] + f[6], s7 = f[7] + f[8],
+          s9 = f[9] + f[10], s11 = f[11] + f[12], s13 = f[13] + f[14], s15 = f[15] + f[16],
+          s17 = f[17] + f[18];
+  return f[0] + ((((s1 + s3) + (s5 + s7)) + ((s9 + s11) + (s13 + s15))) + s17);
+}
+
 // Moments of an offset population set: delta_rho and j.
 template <typename C>
 __device__ __forceinline__ void moments(const C* f, C& drho, C& jx, C& jy, C& jz) {
-  drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) +
-         ((f[8] + f[9]) + (f[10] + f[11])) + ((f[12] + f[13]) + (f[14] + f[15])) +
-         ((f[16] + f[17]) + f[18]);
+  drho = delta_rho(f);
   jx = ((f[1] - f[2]) + (f[7] - f[8])) + ((f[9] - f[10]) + (f[11] - f[12])) + (f[13] - f[14]);
   jy = ((f[3] - f[4]) + (f[7] - f[8])) + ((f[10] - f[9]) + (f[15] - f[16])) + (f[17] - f[18]);
   jz = ((f[5] - f[6]) + (f[11] - f[12])) + ((f[14] - f[13]) + (f[15] - f[16])) + (f[18] - f[17]);
@@ -258,9 +269,7 @@ __device__ __forceinline__ void collide(C* f, const StepK<C>& k, C fon) {
   const C d1 = f[1] - f[2], d3 = f[3] - f[4], d5 = f[5] - f[6], d7 = f[7] - f[8],
           d9 = f[9] - f[10], d11 = f[11] - f[12], d13 = f[13] - f[14], d15 = f[15] - f[16],
           d17 = f[17] - f[18];
-  const C drho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) +
-                 ((f[8] + f[9]) + (f[10] + f[11])) + ((f[12] + f[13]) + (f[14] + f[15])) +
-                 ((f[16] + f[17]) + f[18]);
+  const C drho = delta_rho(f);
   C jx = ((d1 + d7) + (d9 + d11)) + d13;
   C jy = ((d3 + d7) - (d9 - d15)) + d17;
   C jz = ((d5 + d11) - (d13 - d15)) - d17;

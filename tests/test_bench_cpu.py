@@ -39,3 +39,17 @@ def test_traffic_is_null_for_other_code(tmp_path, monkeypatch):
     src.write_text("int g() { return 3; }\n")
     monkeypatch.setattr(b, "KERNEL_SRCS", [str(src)])
     assert b.traffic_entry(1, 1.0) is None
+
+
+def test_gpu_clocks_from_dpm_tables(tmp_path, monkeypatch):
+    b = _bench()
+    dev = tmp_path / "card1" / "device"
+    dev.mkdir(parents=True)
+    (dev / "pp_dpm_sclk").write_text("0: 500Mhz\n1: 1400Mhz\n2: 2400Mhz *\n")
+    (dev / "pp_dpm_mclk").write_text("0: 900Mhz\n1: 2000Mhz *\n")
+    real = b.glob.glob
+    monkeypatch.setattr(b.glob, "glob", lambda pat: real(pat.replace("/sys/class/drm", str(tmp_path))))
+    assert b.gpu_clocks() == {"sclk": "2400Mhz", "mclk": "2000Mhz"}
+    (dev / "pp_dpm_sclk").write_text("0: 500Mhz\n")
+    (dev / "pp_dpm_mclk").unlink()
+    assert b.gpu_clocks() is None
