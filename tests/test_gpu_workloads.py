@@ -14,7 +14,6 @@ from oracle import oracle as O
 from paper_1112_0850_amd import inputs as I
 from paper_1112_0850_amd.lbm import LBM
 from tests.gpu_util import rel_linf, say
-from tests.test_gpu_forward import SLOW_FLOW_F32_TOL
 from tests.test_oracle_dynamics import _poiseuille_exact
 
 pytestmark = pytest.mark.gpu
@@ -51,9 +50,9 @@ def test_channel_startup_full_size(storage):
 
 
 # FP32 storage holds the steady state only to ~ulp(|g|)/2 x H^2/(nu pi^2) /
-# |u| ~ 1.2e-5 (measured 2.5e-5 with FP64 arithmetic): the fixed point of the
-# rounded iteration, whatever the arithmetic.
-@pytest.mark.parametrize("storage,tol", [("f32", SLOW_FLOW_F32_TOL), ("f32x", 4e-5), ("f64", 1e-10)])
+# |u| ~ 1.2e-5 (measured 1.2e-5 with FP32 and 2.5e-5 with FP64 arithmetic):
+# the fixed point of the rounded iteration, whatever the arithmetic.
+@pytest.mark.parametrize("storage,tol", [("f32", 4e-5), ("f32x", 4e-5), ("f64", 1e-10)])
 def test_poiseuille_exact_steady_state_gpu(storage, tol):
     ny, tau, F = 32, 0.6, 1e-6
     shape = (4, ny, 64)
@@ -72,15 +71,16 @@ def test_poiseuille_exact_steady_state_gpu(storage, tol):
 def test_porous_crop_errors_all_storages():
     """128^3 crop of the 512^3 bench geometry, tau = 0.55, g_x = 1e-6, from
     rest, 1000 steps, against the FP64 oracle (errors every 200 steps).
-    FP32 and F32X within 1e-5 on rho and u (observed 8.8e-6 and 7e-8 for u at
-    step 1000; the FP32 error grows with the flow); FP16 and BF16 errors are
-    stated, with bounds of about three times the observed values as a guard
-    against regressions."""
+    The stated bar is 1e-5 relative L-inf on rho and u; FP32 is held to 1e-6
+    here (observed 2.3e-7 for u at step 1000 with the compensated momentum
+    arithmetic, 8.7e-6 without it) and F32X to 1e-6 (observed 7e-8).  FP16
+    and BF16 errors are stated, with bounds of about three times the observed
+    values as a guard against regressions."""
     steps, chunk, tau, F = 1000, 200, 0.55, (1e-6, 0.0, 0.0)
     flags = np.ascontiguousarray(I.sphere_pack((512, 512, 512), 0.10, seed=12345)[:128, :128, :128])
     shape = flags.shape
     fl = (flags & 1) == 0
-    bars = {"f32": 1e-5, "f32x": 1e-5, "f16": 2e-3, "bf16": 2e-2}
+    bars = {"f32": 1e-6, "f32x": 1e-6, "f16": 2e-3, "bf16": 2e-2}
     sims = {st: LBM(shape, tau, F, st, flags=flags, f16_scale_log2=s)
             for st, s in (("f32", 0), ("f32x", 0), ("f16", 12), ("bf16", 0))}
     f = O.init(shape, flags)
@@ -99,4 +99,4 @@ def test_porous_crop_errors_all_storages():
             e_u = rel_linf(u, u_r, fl)
             say(f"  {st}: rel L-inf rho {e_rho:.2e}  delta-rho {e_drho:.2e}  u {e_u:.2e}  "
                 f"mass drift {abs(m[0] - m0) / m0:.2e}")
-            assert e_u <= bars[st] and e_rho <= max(bars[st], 1e-5), (st, t)
+            assert e_u <= bars[st] and e_rho <= bars[st], (st, t)
