@@ -367,19 +367,44 @@ def traffic_entry(alg_bytes, ms):
     return t.get("traffic_bytes_per_launch")
 
 
-KERNELS = {  # kernel-name prefix -> (storage, algorithmic bytes per fluid update)
-    "void lbm::k_step<0, 1, true, false, 1>": ("f32", 152),
-    "void lbm::k_step<1, 1, true, false, 4>": ("f16", 76),
-    "void lbm::k_step<2, 1, true, false, 4>": ("bf16", 76),
-    "void lbm::k_step<3, 1, true, false, 1>": ("f64", 304),
-    "void lbm::k_step<4, 1, true, false, 1>": ("f32x", 152),
+def traffic_record(key):
+    """The committed counter record of one kernel (see KERNELS), or None when
+    the code changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE))
+    if t.get("code_sha256") != code_hash():
+        return None
+    return t.get("kernels", {}).get(key)
+
+
+KERNELS = {  # record key -> (kernel name, box edge, bytes per fluid update, porous 512 geometry)
+    "f32": ("void lbm::k_step<0, 1, true, false, 1>", 512, 152, True),
+    "f16": ("void lbm::k_step<1, 1, true, false, 4>", 512, 76, True),
+    "bf16": ("void lbm::k_step<2, 1, true, false, 4>", 512, 76, True),
+    "f64": ("void lbm::k_step<3, 1, true, false, 1>", 512, 304, True),
+    "f32x": ("void lbm::k_step<4, 1, true, false, 1>", 512, 152, True),
+    "adjoint": ("void lbm::k_adj_step<false>", 256, 228, False),  # periodic, no flags
 }
 
 
+def launch_threads(name, n):
+    """Threads a launch of the named kernel has on an n^3 box (64 * M-cell
+    segments per row, four per block, M = 4 for the 16-bit step kernels)."""
+    m = 4 if name.startswith("void lbm::k_step<1,") or name.startswith("void lbm::k_step<2,") else 1
+    nseg = -(-n // (64 * m))
+    return -(-nseg * n * n // 4) * 256
+
+
+def box_of(name, grid):
+    return next((n for n in (128, 256, 512, 640, 768) if launch_threads(name, n) == grid), None)
+
+
 def profile_summary(trace_dir, fetch_dir, write_dir, n=512):
-    """Summarise the rocprofv3 runs of this script: average kernel durations,
-    and HBM traffic per dispatch from FETCH_SIZE / WRITE_SIZE (KiB), each
-    calibrated by the same counter on the copy kernel of known size."""
+    """Summarise the rocprofv3 runs of this script per kernel and box size:
+    average duration from the per-dispatch kernel trace, and HBM traffic per
+    dispatch from FETCH_SIZE / WRITE_SIZE (KiB), each calibrated by the same
+    counter on the copy kernel of known size."""
     import csv
     import glob
     import numpy as np
@@ -391,42 +416,47 @@ def profile_summary(trace_dir, fetch_dir, write_dir, n=512):
             raise FileNotFoundError(pattern)
         return hits[0]
 
-    stats = list(csv.DictReader(open(one(os.path.join(trace_dir, "*kernel_stats.csv")))))
+    times = {}
+    for r in csv.DictReader(open(one(os.path.join(trace_dir, "*kernel_trace.csv")))):
+        key = (r["Kernel_Name"].split("(")[0], int(r["Grid_Size_X"]))
+        times.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     counters = {}
     for d, cname in ((fetch_dir, "FETCH_SIZE"), (write_dir, "WRITE_SIZE")):
         for r in csv.DictReader(open(one(os.path.join(d, "*counter_collection.csv")))):
             if r["Counter_Name"] == cname:
-                counters.setdefault((r["Kernel_Name"], cname), []).append(float(r["Counter_Value"]))
-    copy_name = next(k for k, _ in counters if k.startswith("lbm::k_copy"))
+                key = (r["Kernel_Name"].split("(")[0], int(r["Grid_Size"]), cname)
+                counters.setdefault(key, []).append(float(r["Counter_Value"]))
+    copy_keys = [k for k in counters if k[0].startswith("lbm::k_copy")]
     copy_bytes = 4 << 30  # the copy leg moves 4 GiB in, 4 GiB out
-    scale = {c: copy_bytes / (1024 * np.mean(counters[(copy_name, c)]))
+    scale = {c: copy_bytes / (1024 * np.mean([v for k in copy_keys if k[2] == c for v in counters[k]]))
              for c in ("FETCH_SIZE", "WRITE_SIZE")}
     flags = I.sphere_pack((n, n, n), 0.10, seed=12345)
-    n_fluid, n_cells = int((flags & 1 == 0).sum()), n ** 3
-    lines = ["| kernel | calls | avg us | fetch GB | write GB | alg GB | traffic/alg |",
-             "|---|---|---|---|---|---|---|"]
+    n_fluid = int((flags & 1 == 0).sum())
+    total = sum(sum(v) for v in times.values())
+    lines = ["| kernel | box | calls | avg us | fetch GB | write GB | alg GB | traffic/alg | actual TB/s |",
+             "|---|---|---|---|---|---|---|---|---|"]
     record = {}
-    for r in stats:
-        name = r["Name"]
-        avg_us = float(r["AverageNs"]) / 1e3
-        row = [name.split("(")[0][:48], r["Calls"], f"{avg_us:.1f}"]
-        key = next((k for k in KERNELS if name.startswith(k)), None)
-        fk, wk = (name, "FETCH_SIZE"), (name, "WRITE_SIZE")
+    for (name, grid), v in sorted(times.items(), key=lambda kv: -sum(kv[1])):
+        avg_us = float(np.mean(v))
+        box = box_of(name, grid) if name.startswith("void lbm::k_") else None
+        row = [name.replace("void ", "")[:44], f"{box}^3" if box else "", str(len(v)), f"{avg_us:.1f}"]
+        rec_key = next((k for k, (kn, kb, _, _) in KERNELS.items() if kn == name and kb == box), None)
+        fk, wk = (name, grid, "FETCH_SIZE"), (name, grid, "WRITE_SIZE")
         if fk in counters and wk in counters:
-            fb = np.mean(counters[fk]) * 1024 * scale["FETCH_SIZE"]
-            wb = np.mean(counters[wk]) * 1024 * scale["WRITE_SIZE"]
+            fb = float(np.mean(counters[fk])) * 1024 * scale["FETCH_SIZE"]
+            wb = float(np.mean(counters[wk])) * 1024 * scale["WRITE_SIZE"]
             row += [f"{fb / 1e9:.2f}", f"{wb / 1e9:.2f}"]
-            if key:
-                st, bpu = KERNELS[key]
-                alg = bpu * n_fluid + n_cells
-                row += [f"{alg / 1e9:.2f}", f"{(fb + wb) / alg:.3f}"]
-                record[st] = {"kernel": key, "avg_us": avg_us, "fetch_bytes": fb,
-                              "write_bytes": wb, "alg_bytes": alg}
+            if rec_key:
+                _, kb, bpu, porous = KERNELS[rec_key]
+                alg = bpu * n_fluid + n ** 3 if porous else bpu * kb ** 3
+                row += [f"{alg / 1e9:.2f}", f"{(fb + wb) / alg:.3f}", f"{(fb + wb) / avg_us / 1e6:.2f}"]
+                record[rec_key] = {"kernel": name, "box": box, "avg_us": avg_us, "fetch_bytes": fb,
+                                   "write_bytes": wb, "alg_bytes": alg}
             else:
-                row += ["", ""]
+                row += ["", "", f"{(fb + wb) / avg_us / 1e6:.2f}"]
         else:
-            row += ["", "", "", ""]
-        if float(r["Percentage"]) > 0.05 or key:
+            row += ["", "", "", "", ""]
+        if sum(v) / total > 0.002 or rec_key:
             lines.append("| " + " | ".join(row) + " |")
     out = {"code_sha256": code_hash(), "fetch_scale": scale["FETCH_SIZE"],
            "write_scale": scale["WRITE_SIZE"], "kernels": record}
@@ -561,6 +591,12 @@ def main():
     if "adjoint" in res:
         line["adjoint"] = res["adjoint"]
         line["adjoint_256"] = res["adjoint_256"]
+        rec = traffic_record("adjoint")
+        if rec:  # measured HBM traffic of the adjoint kernel at 256^3 (rocprofv3 counters)
+            tb = rec["fetch_bytes"] + rec["write_bytes"]
+            line["adjoint_256"]["kernel_traffic"] = {
+                "bytes_per_launch": tb, "over_algorithmic": tb / rec["alg_bytes"],
+                "actual_gbs": tb / res["adjoint_256"]["adj_step_ms"] / 1e6}
     if "large" in res:
         line["large"] = res["large"]
     if "cavity" in res:
