@@ -274,12 +274,13 @@ lbm_status lbm_stream_copy(void* c, const void* a, size_t n_bytes, void* stream)
  * stream; only the step kernels are recorded) and launches the remaining
  * n mod G steps one by one; results are bit-identical to plain launches.
  * 0 (the default) launches every step.  The HIP runtime owns the graphs'
- * resources; changing G or destroying the context waits for the stream and
+ * resources; changing G or destroying the context waits for the latest
+ * replay (on the stream it was queued on, also after lbm_set_stream) and
  * releases them.  Errors: LBM_E_ARG, LBM_E_HIP. */
 lbm_status lbm_use_graphs(lbm_ctx* ctx, int32_t steps_per_graph);
 
 /* Destroys a context: its host memory and, if graphs were used, the graphs
- * (after waiting for the context's stream); device memory stays the caller's. */
+ * (after waiting for their latest replay); device memory stays the caller's. */
 void lbm_destroy(lbm_ctx* ctx);
 
 /* Message of the calling thread's latest error ("" if none). */

@@ -118,6 +118,7 @@ struct lbm_ctx {
   int32_t graph_steps;         // 0: one launch per step; else replay graphs of this many steps
   hipGraphExec_t graph[2];     // per starting grid, captured on first use
   hipStream_t capture_stream;  // library-owned, used only to capture the graphs
+  hipStream_t replay_stream;   // stream of the latest graph replay (may predate lbm_set_stream)
 };
 
 namespace {
@@ -143,12 +144,20 @@ lbm_status launch_steps(lbm_ctx* c, const void* src, void* dst) {
   return launch_steps_on(c, src, dst, c->stream);
 }
 
-void drop_graphs(lbm_ctx* c) {
+// Waits for the latest replay (on whatever stream it was queued), then
+// destroys the executable graphs.
+hipError_t drop_graphs(lbm_ctx* c) {
+  hipError_t e = hipSuccess;
+  if (c->replay_stream) {
+    e = hipStreamSynchronize(c->replay_stream);
+    c->replay_stream = nullptr;
+  }
   for (int p = 0; p < 2; ++p)
     if (c->graph[p]) {
       (void)hipGraphExecDestroy(c->graph[p]);
       c->graph[p] = nullptr;
     }
+  return e;
 }
 
 // Captures graph_steps alternating steps starting from grid `parity` (an
@@ -258,6 +267,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* grid_a, void* grid
   c->graph_steps = 0;
   c->graph[0] = c->graph[1] = nullptr;
   c->capture_stream = nullptr;
+  c->replay_stream = nullptr;
   hipError_t e = lbm::launch_fill_zero(grid_a, sz.grid_bytes, c->stream);
   if (e == hipSuccess) e = lbm::launch_fill_zero(grid_b, sz.grid_bytes, c->stream);
   if (e == hipSuccess)
@@ -281,6 +291,7 @@ lbm_status lbm_step(lbm_ctx* c, int32_t n) {
     }
     hipError_t e = hipGraphLaunch(c->graph[c->cur], c->stream);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
+    c->replay_stream = c->stream;
     n -= c->graph_steps;
     c->t += c->graph_steps;
   }
@@ -443,11 +454,8 @@ lbm_status lbm_use_graphs(lbm_ctx* c, int32_t steps_per_graph) {
     return fail(LBM_E_ARG, "steps_per_graph must be 0 or an even count in [2, 4096] (got %d)",
                 steps_per_graph);
   if (steps_per_graph != c->graph_steps) {
-    if (c->graph[0] || c->graph[1]) {
-      hipError_t e = hipStreamSynchronize(c->stream);  // no replay of the old graphs in flight
-      if (e != hipSuccess) return hip_fail(e, "stream synchronize");
-    }
-    drop_graphs(c);
+    hipError_t e = drop_graphs(c);  // no replay of the old graphs left in flight
+    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
     c->graph_steps = steps_per_graph;
   }
   return LBM_OK;
@@ -455,10 +463,7 @@ lbm_status lbm_use_graphs(lbm_ctx* c, int32_t steps_per_graph) {
 
 void lbm_destroy(lbm_ctx* c) {
   if (!c) return;
-  if (c->graph[0] || c->graph[1]) {
-    (void)hipStreamSynchronize(c->stream);
-    drop_graphs(c);
-  }
+  (void)drop_graphs(c);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
   delete c;
 }

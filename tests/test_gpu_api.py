@@ -77,6 +77,31 @@ def test_steps_on_another_stream_match_the_default_stream():
     assert torch.equal(_bytes(ref), _bytes(other))
 
 
+def test_graph_replays_across_a_stream_change():
+    """Graphs replayed on one stream, the context moved to a second stream,
+    replays there, then the graph length changed and the context destroyed:
+    the results match plain launches and the graphs of the first stream are
+    released only after their replays (waited on the stream they ran on)."""
+    say("graph replays across lbm_set_stream")
+    ref = _sim().step(8 * 5 + 3)
+    g = _sim().use_graphs(8)
+    g.step(16)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    A.lbm_set_stream(g.ctx, ctypes.c_void_p(s.cuda_stream))
+    g.stream = s
+    g.step(8 * 3 + 3)
+    g.use_graphs(4)  # waits for the latest replay, on s
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert g.t == ref.t and torch.equal(_bytes(g), _bytes(ref))
+    g.step(4)
+    ref.step(4)
+    s.synchronize()
+    assert torch.equal(_bytes(g), _bytes(ref))
+    del g
+
+
 def test_interleaved_contexts_are_independent():
     say("interleaved contexts")
     a, b = _sim("f32"), _sim("f16", f16_scale_log2=10)
