@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic porous box")
     ap.add_argument("--only", default="",
                     help="comma list of legs: f32,f16,bf16,f64,f32x,adjoint,copy,cpu,large,cavity,"
-                         "split")
+                         "split,incomp")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--sweep", action="store_true",
                     help="domain-size sweep instead of the headline run: periodic all-fluid cubes "
@@ -488,7 +488,7 @@ def main():
 
     legs = set(args.only.split(",")) if args.only else {"f32", "f16", "bf16", "f64", "f32x",
                                                         "adjoint", "copy", "cpu", "large", "cavity",
-                                                        "split"}
+                                                        "split", "incomp"}
     n = args.n
     log(f"geometry: {n}^3 sphere pack, 10% solid, seed 12345")
     flags = I.sphere_pack((n, n, n), 0.10, seed=12345)
@@ -533,6 +533,13 @@ def main():
                                     args.warmup, s, obstacle_kernel=1)
                         for st, s in (("f32", 0), ("f16", 12))]
         log("  " + ", ".join(f"{c['mlups']:.0f}" for c in res["split"]) + " MLUPS")
+    if "incomp" in legs:
+        # the He-Luo incompressible equilibrium on the same porous workload
+        log("incompressible equilibrium, f32 and f16")
+        res["incomp"] = [forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st, aux,
+                                     args.warmup, s, equilibrium="incompressible")
+                         for st, s in (("f32", 0), ("f16", 12))]
+        log("  " + ", ".join(f"{c['mlups']:.0f}" for c in res["incomp"]) + " MLUPS")
     if "cavity" in legs:
         log(f"lid-driven cavity {n}^3, f32 and f16")
         res["cavity"] = [cavity_leg(torch, "f32", n, aux, args.warmup),
@@ -603,6 +610,8 @@ def main():
         line["cavity"] = res["cavity"]
     if "split" in res:
         line["split_obstacle_kernel"] = res["split"]
+    if "incomp" in res:
+        line["incompressible_equilibrium"] = res["incomp"]
     if "copy" in res:
         line["copy_gbs"] = res["copy"]["gbs"]
         if main_leg:
