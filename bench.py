@@ -55,6 +55,10 @@ def parse():
                     help="domain-size sweep instead of the headline run: periodic all-fluid cubes "
                          "N^3, padded (x_stride multiple of 64) vs unpadded, FP32/FP16/FP64; "
                          "prints one JSON line per point")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
+                    help="summarise a rocprofv3 kernel trace of the default run of this script "
+                         "(split by kernel and box size, checked against the bench line it "
+                         "printed) as markdown on stdout and exit")
     ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="summarise rocprofv3 CSV output (kernel trace, FETCH_SIZE and "
                          "WRITE_SIZE passes of this script) into profiles/ and exit")
@@ -471,8 +475,50 @@ def profile_summary(trace_dir, fetch_dir, write_dir, n=512):
     return 0
 
 
+def trace_summary(trace_dir, bench_json):
+    """Markdown table of a kernel trace of `python bench.py`, per kernel and
+    box size, with the headline kernels' timed launches set against the
+    bench line of the same run."""
+    import csv
+    import glob
+    import statistics
+    path = glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0]
+    rows = sorted(csv.DictReader(open(path)), key=lambda r: int(r["Start_Timestamp"]))
+    d = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    groups, total = {}, 0
+    for r in rows:
+        dur = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        total += dur
+        groups.setdefault((r["Kernel_Name"].split("(")[0], int(r["Grid_Size_X"])), []).append(dur)
+    out = ["| kernel | box | calls | avg us | min us | max us | share of GPU time |",
+           "|---|---|---|---|---|---|---|"]
+    for (name, grid), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        if sum(v) / total < 0.002:
+            continue
+        box = box_of(name, grid) if name.startswith("void lbm::k_") else None
+        out.append(f"| {name.replace('void ', '')} | {f'{box}^3' if box else ''} | {len(v)} | "
+                   f"{statistics.mean(v):.1f} | {min(v):.1f} | {max(v):.1f} | {100 * sum(v) / total:.1f}% |")
+    steps, warm = d["steps"], d["warmup"]
+    out.append("")
+    for key, label, ms in (("f32", "FP32", d["ms_per_step"]),
+                           ("f16", "FP16", d.get("f16_storage", {}).get("ms_per_step"))):
+        name = KERNELS[key][0]
+        n = round(d["config"]["cells"] ** (1 / 3))
+        v = groups.get((name, launch_threads(name, n)), [])
+        if ms and len(v) >= steps + warm:
+            timed = v[warm:warm + steps]
+            out.append(f"{label}: the bench line reports {ms * 1e3:.1f} us per step (HIP events around "
+                       f"{steps} timed steps); the trace's {steps} launches after the {warm} warm-up "
+                       f"launches of {name.replace('void ', '')} at {n}^3 average "
+                       f"{statistics.mean(timed):.1f} us.")
+    print("\n".join(out))
+    return 0
+
+
 def main():
     args = parse()
+    if args.trace_summary:
+        return trace_summary(*args.trace_summary)
     if args.profile_summary:
         return profile_summary(*args.profile_summary)
     if args.gpus != 1:
