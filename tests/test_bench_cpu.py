@@ -1,6 +1,8 @@
-"""Host-side checks of bench.py (CPU): the one-GPU refusal and the code hash
-that keeps the measured traffic attached to the code it was taken on."""
+"""Host-side checks of bench.py (CPU): the one-GPU refusal, the code hash
+that keeps the measured traffic attached to the code it was taken on, the
+clock reading, and the launch-geometry bookkeeping of the profile summaries."""
 import importlib.util
+import json
 import os
 import subprocess
 import sys
@@ -53,3 +55,33 @@ def test_gpu_clocks_from_dpm_tables(tmp_path, monkeypatch):
     (dev / "pp_dpm_sclk").write_text("0: 500Mhz\n")
     (dev / "pp_dpm_mclk").unlink()
     assert b.gpu_clocks() is None
+
+
+def test_launch_geometry_identifies_the_box():
+    b = _bench()
+    f32 = "void lbm::k_step<0, 1, true, false, 1>"
+    f16 = "void lbm::k_step<1, 1, true, false, 4>"
+    assert b.launch_threads(f32, 512) == 512 ** 3  # 64-cell runs, 4 per 256-thread block
+    assert b.launch_threads(f16, 512) == 512 ** 3 // 4  # 4 cells per lane
+    assert b.box_of(f32, 768 ** 3) == 768 and b.box_of(f16, 512 ** 3 // 4) == 512
+    assert b.box_of("void lbm::k_adj_step<false>", 256 ** 3) == 256
+    assert b.box_of(f32, 12345) is None
+
+
+def test_trace_summary_against_the_bench_line(tmp_path, capsys):
+    b = _bench()
+    f32 = "void lbm::k_step<0, 1, true, false, 1>"
+    cols = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X"]
+    lines = [",".join(cols)]
+    t = 0
+    for k in range(6):  # 2 warm-up launches of 5 us, then 4 timed launches of 3 us
+        dur = 5000 if k < 2 else 3000
+        lines.append(f'"{f32}(args)",{t},{t + dur},{512 ** 3}')
+        t += dur + 100
+    (tmp_path / "x_kernel_trace.csv").write_text("\n".join(lines) + "\n")
+    line = {"steps": 4, "warmup": 2, "ms_per_step": 0.003, "config": {"cells": 512 ** 3}}
+    (tmp_path / "b.json").write_text(json.dumps(line) + "\n")
+    assert b.trace_summary(str(tmp_path), str(tmp_path / "b.json")) == 0
+    out = capsys.readouterr().out
+    assert "| lbm::k_step<0, 1, true, false, 1> | 512^3 | 6 | 3.7 | 3.0 | 5.0 |" in out
+    assert "4 launches after the 2 warm-up launches" in out and "average 3.0 us" in out
