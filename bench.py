@@ -88,10 +88,28 @@ def timed_steps(sim, torch, steps, warmup, clocks=None):
     return e0.elapsed_time(e1) / steps
 
 
+def pull_copy_ms(sim, torch, reps=40):
+    """Average time of the pull-copy probe on this grid layout (current grid
+    into the other one, which the next step overwrites anyway)."""
+    src, dst = sim.grids[sim.current], sim.grids[sim.current ^ 1]
+    for _ in range(3):
+        sim.pull_copy(src, dst)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    for _ in range(reps):
+        sim.pull_copy(src, dst)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s=0,
-                fields=None, clocks=None, **kw):
+                fields=None, clocks=None, pull=False, **kw):
     """Times `steps` steps after `warmup`; with a dict `fields`, stores the
-    final (rho, u) there (FP64, on the GPU) for the cross-storage comparison."""
+    final (rho, u) there (FP64, on the GPU) for the cross-storage comparison;
+    with `pull`, also times the pull-copy probe on the same grids."""
     from paper_1112_0850_amd import _abi as A
     n = round(n_cells ** (1 / 3))
     sim = LBM((n, n, n), 0.55, (1e-6, 0.0, 0.0), storage, flags=flags_t, f16_scale_log2=s, **kw)
@@ -99,6 +117,7 @@ def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s
     r = sim.reduce().cpu().numpy()
     if fields is not None:
         fields[storage] = sim.macroscopics(f64=True)
+    pc = pull_copy_ms(sim, torch) if pull else None
     bpu = A.lbm_bytes_per_update(sim.storage)
     alg_bytes = bpu * n_fluid + n_cells  # populations of fluid cells + one flag byte per cell
     out = {
@@ -110,6 +129,10 @@ def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s
     }
     if storage == "f16":
         out["f16_scale_log2"] = s
+    if pc:
+        # the same loads and stores without geometry or collision, all cells
+        out["pull_copy"] = {"ms": pc, "gbs": bpu * n_cells / pc / 1e6,
+                            "step_time_over_probe": ms / pc}
     del sim
     torch.cuda.empty_cache()
     return out
@@ -554,7 +577,8 @@ def main():
             res[st] = forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st,
                                   args.steps if head else aux, args.warmup, s,
                                   fields=fields if head else None,
-                                  clocks=clocks if st == "f32" else None)
+                                  clocks=clocks if st == "f32" else None,
+                                  pull=st in ("f32", "f16"))
             log(f"  {res[st]['mlups']:.0f} MLUPS, {res[st]['alg_gbs']:.0f} GB/s algorithmic")
     if "f32" in fields:
         # 16-bit storage against FP32 storage on the full box at the same step
@@ -662,6 +686,9 @@ def main():
         line["copy_gbs"] = res["copy"]["gbs"]
         if main_leg:
             line["frac_of_copy_bw"] = main_leg["alg_gbs"] / res["copy"]["gbs"]
+    if main_leg and "pull_copy" in main_leg:
+        # the step's own access pattern without geometry or collision (lbm_pull_copy)
+        line["pull_copy_probe"] = dict(main_leg["pull_copy"])
     props = torch.cuda.get_device_properties(0)
     line["device"] = f"{props.name} ({getattr(props, 'gcnArchName', '?')}, "\
                      f"{props.multi_processor_count} CUs, {props.total_memory / 2**30:.0f} GiB)"

@@ -270,6 +270,16 @@ lbm_status lbm_adjoint_finish_dF(lbm_ctx* ctx, const double* dLdF_partials, doub
  * pointers 256-byte aligned, n_bytes a multiple of 16. */
 lbm_status lbm_stream_copy(void* c, const void* a, size_t n_bytes, void* stream);
 
+/* The same model with the access pattern of the step itself: one pure
+ * streaming pass dst_i(x) = src_i(x - c_i) over the context's grid layout
+ * (periodic in every axis; flags, walls and collision ignored), launched
+ * exactly like the step kernel -- 19 shifted loads and 19 full-line stores
+ * per cell.  Its rate is the bandwidth this memory pattern attains on the
+ * device, the denominator that isolates the step's own overheads.  src and
+ * dst are distinct grids of grid_bytes (256-byte aligned); the context's
+ * grids and time level are untouched.  Errors: LBM_E_ARG, LBM_E_HIP. */
+lbm_status lbm_pull_copy(lbm_ctx* ctx, const void* src, void* dst);
+
 /* Launch-bound runs (small grids): with steps_per_graph = G (even, 2..4096)
  * lbm_step replays HIP graphs of G captured steps on the context's stream
  * (one graph per starting grid, captured on first use on a library-owned

@@ -58,6 +58,7 @@ _SIGNATURES = {
     "lbm_adjoint_init": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_adjoint_finish_dF": (_st, [_vp, _vp, _vp]),
     "lbm_stream_copy": (_st, [_vp, _vp, C.c_size_t, _vp]),
+    "lbm_pull_copy": (_st, [_vp, _vp, _vp]),
     "lbm_use_graphs": (_st, [_vp, C.c_int32]),
     "lbm_destroy": (None, [_vp]),
     "lbm_last_error": (C.c_char_p, []),
@@ -202,6 +203,10 @@ def lbm_adjoint_finish_dF(ctx, partials, dLdF3):
 
 def lbm_stream_copy(dst, src, n_bytes, stream):
     check(lib().lbm_stream_copy(dst, src, int(n_bytes), stream))
+
+
+def lbm_pull_copy(ctx, src, dst):
+    check(lib().lbm_pull_copy(ctx, src, dst))
 
 
 def lbm_use_graphs(ctx, steps_per_graph):

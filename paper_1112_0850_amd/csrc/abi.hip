@@ -447,6 +447,16 @@ lbm_status lbm_stream_copy(void* dst, const void* src, size_t n_bytes, void* str
   return e == hipSuccess ? LBM_OK : hip_fail(e, "copy launch");
 }
 
+lbm_status lbm_pull_copy(lbm_ctx* c, const void* src, void* dst) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!src || !dst) return fail(LBM_E_ARG, "src and dst must not be NULL");
+  if (src == dst) return fail(LBM_E_ARG, "src and dst must differ");
+  if (!aligned256(src) || !aligned256(dst)) return fail(LBM_E_ARG, "src/dst must be 256-byte aligned");
+  hipError_t e = lbm::launch_pull_copy(c->p.storage, c->geo, src, dst, c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "pull-copy launch");
+}
+
 lbm_status lbm_use_graphs(lbm_ctx* c, int32_t steps_per_graph) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;

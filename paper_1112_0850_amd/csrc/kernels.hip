@@ -430,6 +430,9 @@ __device__ __forceinline__ void collide(C* f, const StepK<C>& k, C fon) {
 // separate kernel, Sec. 7): k_obstacle has already written the bounce-back
 // values into the solid cells' slots of src, so the step pulls with no
 // marker test at all; flags still give the solid and no-force bits.
+// WALLS = 4 is the pull-copy probe: the same loads and stores with neither
+// geometry nor collision, f_i(x) <- f_i(x - c_i) on a periodic box -- the
+// speed this memory pattern itself allows.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ void stream_store(T* p, T v) {
@@ -459,8 +462,9 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
   using C = typename Storage<K>::C;
   using T = typename Storage<K>::T;
   constexpr bool SCALED = (K == ST_F16);
-  constexpr bool SOLIDS = WALLS != 0;
+  constexpr bool SOLIDS = WALLS >= 1 && WALLS <= 3;
   constexpr bool MARKERS = WALLS == 1 || WALLS == 2;
+  constexpr bool COPY = WALLS == 4;
   // g describes 64*M-cell segments (step_geo); same block remap as locate().
   const int b = blockIdx.x;
   const int lb = (b < g.nb8) ? ((b & 7) * (g.nb8 >> 3) + (b >> 3)) : b;
@@ -521,10 +525,12 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     // Solid lanes run the collision on their (meaningless) pulls and discard it.
-    if (FORCE && SOLIDS)
+    if (COPY) {
+    } else if (FORCE && SOLIDS) {
       collide<C, FORCE, SCALED, INC, K == ST_F32>(f[m], k, (fl[m] & FLAG_NOFORCE) ? C(0) : C(1));
-    else
+    } else {
       collide<C, FORCE, SCALED, INC, K == ST_F32>(f[m], k, C(1));
+    }
     const C marker = solid_marker<C>(fl[m], WALLS == 2 || (WALLS == 3 && k.moving));
     if (valid[m]) {
 #pragma unroll
@@ -1139,6 +1145,28 @@ hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const
     case ST_BF16: step_k<ST_BF16>(solids, force, g, ph, src, dst, flags, s); break;
     case ST_F64: step_k<ST_F64>(solids, force, g, ph, src, dst, flags, s); break;
     case ST_F32X: step_k<ST_F32X>(solids, force, g, ph, src, dst, flags, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int K>
+static void pull_t(const Geo& g, const void* src, void* dst, hipStream_t s) {
+  using S = Storage<K>;
+  constexpr int M = StepCells<K>::M;
+  const Geo h = step_geo(g, M);
+  hipLaunchKernelGGL((k_step<K, 4, false, false, M>), dim3(h.nblocks), dim3(kBlock), 0, s,
+                     reinterpret_cast<const typename S::T*>(src),
+                     reinterpret_cast<typename S::T*>(dst), nullptr, h, StepK<typename S::C>{});
+}
+
+hipError_t launch_pull_copy(int storage, const Geo& g, const void* src, void* dst, hipStream_t s) {
+  switch (storage) {
+    case ST_F32: pull_t<ST_F32>(g, src, dst, s); break;
+    case ST_F16: pull_t<ST_F16>(g, src, dst, s); break;
+    case ST_BF16: pull_t<ST_BF16>(g, src, dst, s); break;
+    case ST_F64: pull_t<ST_F64>(g, src, dst, s); break;
+    case ST_F32X: pull_t<ST_F32X>(g, src, dst, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

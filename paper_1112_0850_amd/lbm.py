@@ -147,6 +147,12 @@ class LBM:
     def set_current(self, parity, t):
         A.lbm_set_current(self.ctx, parity, t)
 
+    def pull_copy(self, src, dst):
+        """Pull-copy probe: dst_i(x) = src_i(x - c_i) over this grid layout
+        (periodic, no geometry, no collision), launched like the step."""
+        A.lbm_pull_copy(self.ctx, _ptr(_aligned(src, "src")), _ptr(_aligned(dst, "dst")))
+        return self
+
     def use_graphs(self, steps_per_graph):
         """Replay HIP graphs of `steps_per_graph` (even) captured steps in
         step() -- for launch-bound small grids; 0 turns it off."""

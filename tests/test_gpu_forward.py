@@ -65,6 +65,31 @@ def test_free_streaming_closed_form(shape):
 
 
 @pytest.mark.parametrize("storage", STORAGES)
+@pytest.mark.parametrize("shape", [(3, 4, 1), (3, 2, 17), (3, 5, 65), (4, 3, 130)])
+def test_pull_copy_probe_is_the_periodic_shift(storage, shape):
+    """lbm_pull_copy: dst_i(x) = src_i(x - c_i) on the periodic box, bit for
+    bit in every storage and whatever the flags; the x padding of dst and the
+    context's own grids and time level are left untouched."""
+    say("pull-copy probe", storage, shape)
+    e = R.e_w_opp()[0]
+    nz, ny, nx = shape
+    flags = I.random_flags(shape, 3, solid_fraction=0.3)
+    sim = LBM(shape, 0.7, (1e-4, 0, 0), storage, flags=flags)
+    before = [g.clone() for g in sim.grids]
+    src, dst = sim.new_grid().zero_(), sim.new_grid().zero_()
+    g = _round_to(I.random_offsets(shape, 11), storage)
+    sim.grid_view(src)[..., :nx].copy_(torch.from_numpy(g).to(sim.dtype))
+    sim.pull_copy(src, dst)
+    torch.cuda.synchronize()
+    got = sim.grid_view(dst)
+    for i in range(19):
+        ref = np.roll(g[i], shift=(e[i, 2], e[i, 1], e[i, 0]), axis=(0, 1, 2))
+        assert np.array_equal(got[i, ..., :nx].double().cpu().numpy(), ref), i
+    assert not got[..., nx:].any()
+    assert sim.t == 0 and all(torch.equal(a, b) for a, b in zip(before, sim.grids))
+
+
+@pytest.mark.parametrize("storage", STORAGES)
 def test_write_coverage(storage):
     """One step writes every slot of every cell -- fluid cells finite values,
     solid cells the NaN marker -- and never the padding: fill the target
