@@ -578,7 +578,7 @@ def main():
                                   args.steps if head else aux, args.warmup, s,
                                   fields=fields if head else None,
                                   clocks=clocks if st == "f32" else None,
-                                  pull=st in ("f32", "f16"))
+                                  pull=st in ("f32", "f16", "f64"))
             log(f"  {res[st]['mlups']:.0f} MLUPS, {res[st]['alg_gbs']:.0f} GB/s algorithmic")
     if "f32" in fields:
         # 16-bit storage against FP32 storage on the full box at the same step
