@@ -55,6 +55,20 @@ def test_sampled_step_at_full_size(geometry, storage, s):
     _sampled_step(sim, flags, storage, s, rng.choice(fluid, size=256, replace=False), TAU, F, None)
 
 
+@pytest.mark.parametrize("storage,s", [("f32", 0), ("f16", 12)])
+def test_sampled_incompressible_step_at_full_size(geometry, storage, s):
+    """The bench's incompressible-equilibrium legs: the 512^3 porous box with
+    the He-Luo equilibrium, sampled one-step parity."""
+    flags, u0 = geometry
+    say(f"full size {N}^3 porous, incompressible, {storage}: sampled one-step parity")
+    sim = LBM((N, N, N), TAU, F, storage, flags=flags, u0=u0, f16_scale_log2=s,
+              equilibrium="incompressible")
+    rng = np.random.default_rng(2025)
+    fluid = np.flatnonzero((flags & 1 == 0).ravel())
+    _sampled_step(sim, flags, storage, s, rng.choice(fluid, size=256, replace=False), TAU, F, None,
+                  incompressible=True)
+
+
 CAVITY_TAU, CAVITY_U = 0.55, 0.05
 
 
@@ -77,7 +91,7 @@ def test_sampled_cavity_step_at_full_size(storage, s):
     _sampled_step(sim, flags, storage, s, cells, CAVITY_TAU, (0, 0, 0), (CAVITY_U, 0, 0))
 
 
-def _sampled_step(sim, flags, storage, s, cells, tau, F, wall_u, extra=3):
+def _sampled_step(sim, flags, storage, s, cells, tau, F, wall_u, extra=3, incompressible=False):
     """`extra` more steps, then one: each sampled fluid cell of the last step
     against the oracle's step of its 3^3 neighbourhood, read from the state
     before that step (no copy of the grid is made, so this runs at sizes
@@ -101,7 +115,8 @@ def _sampled_step(sim, flags, storage, s, cells, tau, F, wall_u, extra=3):
     for z, y, x, g, fl in crops:
         f = g + W[:, None, None, None]
         f[:, fl & 1 == 1] = 0
-        ref = O.step(f, tau, F, fl, n=1, wall_u=wall_u)[:, 1, 1, 1] - W
+        ref = O.step(f, tau, F, fl, n=1, wall_u=wall_u,
+                     incompressible=incompressible)[:, 1, 1, 1] - W
         got = cv[:, z, y, x].double().cpu().numpy() / scale
         if storage in ("f32", "f32x"):
             err = np.abs(got - ref)
