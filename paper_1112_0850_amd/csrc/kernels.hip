@@ -439,6 +439,17 @@ __device__ __forceinline__ void stream_store(T* p, T v) {
   __builtin_nontemporal_store(v, p);
 }
 
+// Pins a collision result as a rounded FP32 register value before its FP16
+// store conversion.  Without it the compiler may fold the last fused
+// multiply-add and the conversion into one mixed-precision instruction that
+// rounds once, straight to FP16 -- in some kernel variants and not in
+// others, so that variants differ in the last bit; with it every FP16 store
+// is the FP32 result rounded to nearest even, as in the other storages.
+__device__ __forceinline__ float fp32_result(float v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 template <int WALLS, typename C>
 __device__ __forceinline__ bool is_marker(C v) {
   if (WALLS == 2) return !__builtin_isfinite(v);  // NaN or infinity
@@ -534,8 +545,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
     const C marker = solid_marker<C>(fl[m], WALLS == 2 || (WALLS == 3 && k.moving));
     if (valid[m]) {
 #pragma unroll
-      for (int i = 0; i < Q; ++i)
-        stream_store(elem_rx(dst, pb, i, n[m].row[1][1], n[m].xn[1]), T(solid[m] ? marker : f[m][i]));
+      for (int i = 0; i < Q; ++i) {
+        C out = solid[m] ? marker : f[m][i];
+        if constexpr (K == ST_F16) out = fp32_result(out);
+        stream_store(elem_rx(dst, pb, i, n[m].row[1][1], n[m].xn[1]), T(out));
+      }
     }
   }
 }

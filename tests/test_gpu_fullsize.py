@@ -69,6 +69,52 @@ def test_sampled_incompressible_step_at_full_size(geometry, storage, s):
                   incompressible=True)
 
 
+@pytest.mark.parametrize("storage,s", [("f32", 0), ("f16", 12)])
+def test_split_design_matches_fused_at_full_size(geometry, storage, s):
+    """The bench's split-design legs (separate obstacle kernel) against the
+    fused step on the 512^3 porous box: identical fluid-cell bits after a
+    few steps (the solid cells' slots differ by design: bounce-back values
+    there, markers in the fused grids)."""
+    flags, u0 = geometry
+    say(f"full size {N}^3 porous, {storage}: split design == fused")
+    fused = LBM((N, N, N), TAU, F, storage, flags=flags, u0=u0, f16_scale_log2=s).step(5)
+    split = LBM((N, N, N), TAU, F, storage, flags=flags, u0=u0, f16_scale_log2=s,
+                obstacle_kernel=1).step(5)
+    torch.cuda.synchronize()
+    fluid = torch.from_numpy((flags & 1) == 0).cuda()
+    a, b = fused.populations()[..., :N], split.populations()[..., :N]
+    for i in range(19):
+        assert torch.equal(a[i][fluid], b[i][fluid]), i
+    del fused, split, a, b
+    torch.cuda.empty_cache()
+
+
+def test_pull_copy_probe_at_full_size():
+    """The pull-copy probe as the bench times it (512^3 FP32 layout): sampled
+    cells of dst equal src at x - c_i (periodic)."""
+    from tests import lattice_ref as R
+    say(f"full size {N}^3 pull-copy probe, sampled")
+    e = R.e_w_opp()[0]
+    sim = LBM((N, N, N), TAU, F, "f32")
+    src, dst = sim.new_grid(), sim.new_grid().zero_()
+    sv = sim.grid_view(src)
+    sv.copy_(torch.rand(sv.shape, device="cuda", dtype=torch.float32))
+    sim.pull_copy(src, dst)
+    torch.cuda.synchronize()
+    dv = sim.grid_view(dst)
+    rng = np.random.default_rng(5)
+    zyx = rng.integers(0, N, size=(512, 3))
+    zyx[:8] = [(0, 0, 0), (N - 1, N - 1, N - 1), (0, N - 1, 0), (N - 1, 0, N - 1),
+               (0, 0, N - 1), (N - 1, N - 1, 0), (N // 2, 0, 0), (0, N // 2, N - 1)]
+    for i in range(19):
+        z, y, x = (torch.from_numpy(zyx[:, k]).cuda() for k in range(3))
+        zs, ys, xs = (z - int(e[i, 2])) % N, (y - int(e[i, 1])) % N, (x - int(e[i, 0])) % N
+        assert torch.equal(dv[i, z, y, x], sv[i, zs, ys, xs]), i
+    del sim, src, dst, sv, dv
+    torch.cuda.empty_cache()
+
+
+CAVITY_TAU, CAVITY_U = 0.55, 0.05
 CAVITY_TAU, CAVITY_U = 0.55, 0.05
 
 
