@@ -85,3 +85,42 @@ def test_trace_summary_against_the_bench_line(tmp_path, capsys):
     out = capsys.readouterr().out
     assert "| lbm::k_step<0, 1, true, false, 1> | 512^3 | 6 | 3.7 | 3.0 | 5.0 |" in out
     assert "4 launches after the 2 warm-up launches" in out and "average 3.0 us" in out
+
+
+def test_profile_summary_calibrates_and_records(tmp_path, monkeypatch, capsys):
+    """Synthetic trace and counter CSVs: the copy kernel's 4 GiB read and
+    written calibrate FETCH_SIZE (x2 here) and WRITE_SIZE (x1); the FP32 step
+    at 512^3 gets its traffic per launch, its ratio to the algorithmic bytes
+    and a record in the traffic file, keyed to the code hash."""
+    b = _bench()
+    monkeypatch.setattr(b, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    f32 = "void lbm::k_step<0, 1, true, false, 1>"
+    cp = "lbm::k_copy"
+    tr = tmp_path / "tr"
+    fe = tmp_path / "fe"
+    wr = tmp_path / "wr"
+    for d in (tr, fe, wr):
+        d.mkdir()
+    g = b.launch_threads(f32, 512)
+    rows = ["Kernel_Name,Start_Timestamp,End_Timestamp,Grid_Size_X",
+            f'"{f32}(x)",0,4000000,{g}', f'"{f32}(x)",5000000,9000000,{g}',
+            f'"{cp}(x)",10000000,11400000,268435456']
+    (tr / "t_kernel_trace.csv").write_text("\n".join(rows) + "\n")
+    kib = 1024
+    fetch_f32, write_f32 = 10.0e9, 10.2e9   # bytes the step moves per launch
+    for d, cname, vals in ((fe, "FETCH_SIZE", {f32: fetch_f32 / 2, cp: (4 << 30) / 2}),
+                           (wr, "WRITE_SIZE", {f32: write_f32, cp: 4 << 30})):
+        lines = ["Kernel_Name,Grid_Size,Counter_Name,Counter_Value"]
+        for name, v in vals.items():
+            grid = g if name == f32 else 268435456
+            lines.append(f'"{name}(x)",{grid},{cname},{v / kib}')
+        (d / "c_counter_collection.csv").write_text("\n".join(lines) + "\n")
+    assert b.profile_summary(str(tr), str(fe), str(wr), n=64) == 0
+    out = capsys.readouterr().out
+    assert "FETCH_SIZE x2.0000, WRITE_SIZE x1.0000" in out
+    rec = json.load(open(tmp_path / "traffic.json"))
+    assert rec["code_sha256"] == b.code_hash()
+    k = rec["kernels"]["f32"]
+    assert abs(k["fetch_bytes"] - fetch_f32) < 1 and abs(k["write_bytes"] - write_f32) < 1
+    assert k["box"] == 512 and abs(k["avg_us"] - 4000.0) < 1e-9
+    assert abs(rec["traffic_bytes_per_launch"] - (fetch_f32 + write_f32)) < 1
