@@ -49,6 +49,11 @@ def test_argument_errors_leave_the_context_unchanged():
     assert e.value.status == A.LBM_E_ARG
     with pytest.raises(A.LBMError):
         A.lbm_restore(sim.ctx, None, 0)
+    for src, dst, what in ((P(g), P(g), "differ"), (None, P(other), "NULL"),
+                           (ctypes.c_void_p(g.data_ptr() + 16), P(other), "aligned")):
+        with pytest.raises(A.LBMError) as e:
+            A.lbm_pull_copy(sim.ctx, src, dst)
+        assert e.value.status == A.LBM_E_ARG and what in str(e.value)
     assert sim.t == t and torch.equal(_bytes(sim), before)
     sim.step(1)  # still usable
     assert sim.t == t + 1
