@@ -147,3 +147,13 @@ def test_null_context_rejected():
     assert A.lbm_current(None) == -1 and A.lbm_time(None) == -1
     with pytest.raises(A.LBMError):
         A.lbm_stream_copy(ctypes.c_void_p(0x100), ctypes.c_void_p(0x200), 17, None)
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """Without the built HIP library every call raises: there is no fallback."""
+    monkeypatch.setattr(A, "_lib", None)
+    monkeypatch.setattr(A, "LIB_PATH", str(tmp_path / "liblbm.so"))
+    with pytest.raises(ImportError, match="no CPU fallback"):
+        A.lib()
+    with pytest.raises(ImportError):
+        A.lbm_query(A.params((4, 4, 4), 0.7))
