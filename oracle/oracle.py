@@ -15,6 +15,7 @@ cells with the moving-wall bit, or None) and ``incompressible`` (False: the
 Qian equilibrium with u = j/rho; True: the He-Luo equilibrium, u = j/rho0).
 """
 import ctypes as C
+import os
 
 import numpy as np
 
@@ -57,9 +58,11 @@ def load(path):
 
 
 def lib():
+    """The oracle library: ``liboracle.so``, or the build named by the
+    ORACLE_LIB environment variable (the sanitizer build of the tests)."""
     global _lib
     if _lib is None:
-        _lib = load(_build.ensure_built())
+        _lib = load(os.environ.get("ORACLE_LIB") or _build.ensure_built())
     return _lib
 
 

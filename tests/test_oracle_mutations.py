@@ -15,6 +15,7 @@ from tests import test_oracle_dynamics as TD
 from tests import test_oracle_incompressible as TI
 from tests import test_oracle_lattice as TL
 from tests import test_oracle_streaming as TS
+from tests import test_oracle_switches as TSW
 from tests import test_oracle_walls as TW
 
 SRC = os.path.join(os.path.dirname(O.__file__), "lbm_oracle.c")
@@ -92,6 +93,22 @@ def _walls_full_adj():
     TA.test_full_adjoint_vs_central_differences(True, True, False)
 
 
+def _noforce_gain():
+    TSW.test_noforce_switch_momentum_gain(1)
+
+
+def _noforce_rest():
+    TSW.test_noforce_switch_one_step_from_rest()
+
+
+def _qian_reduce():
+    TSW.test_qian_reduction_of_an_equilibrium_state()
+
+
+def _drho0():
+    TSW.test_initial_density_gradient_vs_central_differences()
+
+
 # (planted change: old text -> new text, first occurrence only; pins that must fail)
 MUTATIONS = {
     "equilibrium_second_order": ("double poly = 3.0 * cu + 4.5 * cu * cu", "double poly = 3.0 * cu + 4.0 * cu * cu",
@@ -146,6 +163,20 @@ MUTATIONS = {
                                    "double du_df = incomp ? (C[jj][a] - u[a]) :", [_inc_jac]),
     "incompressible_jacobian_drho": ("double dfeq_drho = incomp ? W[i] :",
                                      "double dfeq_drho = incomp ? W[i] * (1.0 + poly) :", [_inc_jac]),
+    "noforce_ignored": ("int off = flags && (flags[c] & FLAG_NOFORCE);", "int off = 0;",
+                        [_noforce_gain, _noforce_rest]),
+    "noforce_inverted": ("int off = flags && (flags[c] & FLAG_NOFORCE);",
+                         "int off = !(flags && (flags[c] & FLAG_NOFORCE));",
+                         [_noforce_gain, _noforce_rest]),
+    "macroscopics_noforce_ignored": ("    double Fc[3];\n    cell_force(flags, c, F, Fc);\n    if (rho) rho[c] = r;",
+                                     "    double Fc[3] = {F[0], F[1], F[2]};\n    if (rho) rho[c] = r;",
+                                     [_noforce_rest]),
+    "qian_energy_without_rho": ("s[4] += 0.5 * m * dot3(uc, uc);", "s[4] += 0.5 * dot3(uc, uc);",
+                                [_qian_reduce]),
+    "qian_momentum_without_rho": ("s[1 + d] += m * uc[d];", "s[1 + d] += uc[d];", [_qian_reduce]),
+    "adjoint_init_drho_dropped_uu": ("4.5 * cu * cu - 1.5 * uu));", "4.5 * cu * cu));", [_drho0]),
+    "adjoint_init_drho_dropped_cu": ("W[i] * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu));",
+                                     "W[i] * (1.0 + 4.5 * cu * cu - 1.5 * uu));", [_drho0]),
     "incompressible_seed": ("v += gu[d] * (incomp ? ABI_E[k][d] :",
                             "v += gu[d] * (incomp ? ABI_E[k][d] - uc[d] :", [_inc_full_adj]),
 }
