@@ -19,6 +19,7 @@ import glob
 import hashlib
 import re
 import json
+import math
 import os
 import sys
 import threading
@@ -55,6 +56,8 @@ def parse():
                     help="domain-size sweep instead of the headline run: periodic all-fluid cubes "
                          "N^3, padded (x_stride multiple of 64) vs unpadded, FP32/FP16/FP64; "
                          "prints one JSON line per point")
+    ap.add_argument("--sweep-summary", metavar="SWEEP_JSONL",
+                    help="print the markdown table of a --sweep output file and exit")
     ap.add_argument("--trace-summary", nargs=2, metavar=("TRACE_DIR", "BENCH_JSON"),
                     help="summarise a rocprofv3 kernel trace of the default run of this script "
                          "(split by kernel and box size, checked against the bench line it "
@@ -65,27 +68,42 @@ def parse():
     return ap.parse_args()
 
 
-def timed_steps(sim, torch, steps, warmup, clocks=None):
-    """Average ms per fused step over `steps` launches, HIP events on the
-    solver's stream, bracketed by device synchronisation.  With a dict
-    `clocks`, a timer thread reads the GPU clocks (sysfs) 0.5 s into the
-    timed steps."""
+REPS = 5
+
+
+def timed_steps(sim, torch, steps, warmup, clocks=None, detail=None, reps=REPS):
+    """Milliseconds per fused step: `warmup` untimed steps, then exactly
+    `steps` timed steps bracketed by device synchronisation, split into
+    `reps` consecutive repetitions whose HIP events (recorded on the solver's
+    stream) give one per-step time each; returns their median.  With a dict
+    `detail`, also the minimum, maximum, every repetition and the plain
+    average over all `steps`.  With a dict `clocks`, a timer thread reads the
+    GPU clocks (sysfs) 0.5 s into the timed steps."""
+    import statistics
     sim.step(warmup)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(1, min(reps, steps))
+    sizes = [steps // reps + (1 if r < steps % reps else 0) for r in range(reps)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     timer = None
     if clocks is not None:
         timer = threading.Timer(0.5, lambda: clocks.update(gpu_clocks() or {}))
-    e0.record(sim.stream)
+    ev[0].record(sim.stream)
     if timer:
         timer.start()
-    sim.step(steps)
-    e1.record(sim.stream)
+    for r, n in enumerate(sizes):
+        sim.step(n)
+        ev[r + 1].record(sim.stream)
     torch.cuda.synchronize()
     if timer:
         timer.join()
-    return e0.elapsed_time(e1) / steps
+    per = [ev[r].elapsed_time(ev[r + 1]) / sizes[r] for r in range(reps)]
+    med = statistics.median(per)
+    if detail is not None:
+        detail.update({"reps": reps, "steps_per_rep": sizes, "ms_median": med, "ms_min": min(per),
+                       "ms_max": max(per), "ms_reps": per,
+                       "ms_mean_all": ev[0].elapsed_time(ev[-1]) / steps})
+    return med
 
 
 def pull_copy_ms(sim, torch, reps=40):
@@ -113,7 +131,8 @@ def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s
     from paper_1112_0850_amd import _abi as A
     n = round(n_cells ** (1 / 3))
     sim = LBM((n, n, n), 0.55, (1e-6, 0.0, 0.0), storage, flags=flags_t, f16_scale_log2=s, **kw)
-    ms = timed_steps(sim, torch, steps, warmup, clocks)
+    rep = {}
+    ms = timed_steps(sim, torch, steps, warmup, clocks, detail=rep)
     r = sim.reduce().cpu().numpy()
     if fields is not None:
         fields[storage] = sim.macroscopics(f64=True)
@@ -125,7 +144,8 @@ def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s
         "mlups": n_cells / ms / 1e3, "mflups": n_fluid / ms / 1e3,
         "bytes_per_update": bpu, "alg_bytes_per_step": alg_bytes,
         "alg_gbs": alg_bytes / ms / 1e6, "hbm_frac": alg_bytes / ms / 1e6 / HBM_PEAK_GBS,
-        "mass": float(r[0]), "finite": bool(all(map(lambda v: v == v, r))),
+        "mass": float(r[0]), "finite": bool(all(math.isfinite(float(v)) for v in r)),
+        "timing": rep,
     }
     if storage == "f16":
         out["f16_scale_log2"] = s
@@ -192,30 +212,31 @@ SWEEP_N = (32, 48, 64, 80, 96, 100, 128, 160, 192, 200, 250, 256, 300, 320, 384,
            512, 576, 640, 700, 768)
 
 
-def sweep(torch):
+def sweep(torch, storages=("f32", "f16", "f64"), sizes=SWEEP_N):
     """MLUPS against the edge N of a periodic all-fluid cube (tau 0.6, no
-    force, at rest), with the x-stride padded to 64 cells or not padded.
-    Median of 5 timed repetitions per point; when N is a multiple of 64
-    both layouts are the same and the point is timed once.  Up to N = 160
-    the padded layout is also timed with replayed graphs of 32 steps."""
-    import statistics
+    force, at rest), with the x-stride padded to 64 cells or not padded
+    (the paper's domain sweep with and without padding, Sec. 7).  Each
+    point: the median of 5 timed repetitions (timed_steps); when N is a
+    multiple of 64 both layouts are the same and the point is timed once.
+    Up to N = 160 the padded layout is also timed with replayed graphs of
+    32 steps."""
     from paper_1112_0850_amd.lbm import LBM
-    for st in ("f32", "f16", "f64"):
-        for n in SWEEP_N:
+    for st in storages:
+        for n in sizes:
             for align in (0, 1):
                 if align == 1 and n % 64 == 0:
                     continue
                 sim = LBM((n, n, n), 0.6, (0.0, 0.0, 0.0), st, x_align=align)
                 steps = max(10, min(400, int(2e9 / n ** 3)))
-                ms = statistics.median(timed_steps(sim, torch, steps, max(3, steps // 10))
-                                       for _ in range(5))
+                rep = {}
+                ms = timed_steps(sim, torch, steps, max(3, steps // 10), detail=rep)
                 rec = {"sweep": st, "n": n, "padded": align == 0 or n % 64 == 0,
                        "x_stride": sim.x_stride, "same_layout": n % 64 == 0,
-                       "ms_per_step": ms, "mlups": n ** 3 / ms / 1e3,
-                       "grid_gb": 2 * sim.grid_bytes / 1e9}
+                       "ms_per_step": ms, "ms_min": rep["ms_min"], "ms_max": rep["ms_max"],
+                       "mlups": n ** 3 / ms / 1e3, "grid_gb": 2 * sim.grid_bytes / 1e9}
                 if align == 0 and n <= 160:  # launch-bound sizes: replayed step graphs
                     sim.use_graphs(32)
-                    msg = statistics.median(timed_steps(sim, torch, 320, 64) for _ in range(5))
+                    msg = timed_steps(sim, torch, 320, 64)
                     rec["graph_mlups"] = n ** 3 / msg / 1e3
                 print(json.dumps(rec), flush=True)
                 del sim
@@ -223,26 +244,69 @@ def sweep(torch):
     return 0
 
 
+def sweep_summary(path):
+    """Markdown table of the JSON lines `--sweep` printed (MLUPS, padded /
+    unpadded, per storage and edge N)."""
+    rows = [json.loads(l) for l in open(path) if l.startswith("{")]
+    sts = sorted({r["sweep"] for r in rows}, key=["f32", "f16", "bf16", "f64"].index)
+    ns = sorted({r["n"] for r in rows})
+    out = ["| N | " + " | ".join(f"{st.upper()} padded / unpadded MLUPS" for st in sts) + " |",
+           "|---|" + "---|" * len(sts)]
+    for n in ns:
+        cells = []
+        for st in sts:
+            pad = [r for r in rows if r["sweep"] == st and r["n"] == n and r["padded"]]
+            unp = [r for r in rows if r["sweep"] == st and r["n"] == n and not r["padded"]]
+            c = f"{pad[0]['mlups'] / 1e3:.1f}k" if pad else "-"
+            if unp:
+                c += f" / {unp[0]['mlups'] / 1e3:.1f}k"
+            if pad and "graph_mlups" in pad[0]:
+                c += f" (graphs {pad[0]['graph_mlups'] / 1e3:.1f}k)"
+            cells.append(c)
+        out.append(f"| {n} | " + " | ".join(cells) + " |")
+    print("\n".join(out))
+    return 0
+
+
 def copy_leg(torch):
-    from paper_1112_0850_amd.lbm import stream_copy
+    """STREAM copy c = a of 4 GiB (the paper's Sec. 3 case study): the
+    library's default copy kernel (one 16-byte element per thread), and a
+    sweep over the copy's variants -- 1, 2 or 4 elements per thread per pass,
+    plain or non-temporal accesses, one pass or a grid of 1024-16384 blocks
+    striding through the array -- whose best is the attainable bandwidth
+    (median of 10 timed repetitions each)."""
+    import statistics
+    from paper_1112_0850_amd.lbm import copy_probe, stream_copy
     nbytes = 4 << 30
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     c = torch.empty_like(a)
     a.fill_(1)
-    for _ in range(3):
-        stream_copy(c, a)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 20
-    e0.record()
-    for _ in range(reps):
-        stream_copy(c, a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+
+    def timed(fn, reps=10):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record()
+        for r in range(reps):
+            fn()
+            ev[r + 1].record()
+        torch.cuda.synchronize()
+        return statistics.median(ev[r].elapsed_time(ev[r + 1]) for r in range(reps))
+
+    ms = timed(lambda: stream_copy(c, a))
+    sweep_rows = []
+    for vec in (1, 2, 4):
+        for nt in (False, True):
+            for blocks in (0, 1024, 2048, 4096, 8192, 16384):
+                m = timed(lambda: copy_probe(c, a, vec, nt, blocks))
+                sweep_rows.append({"vec_per_thread": vec, "nontemporal": nt, "blocks": blocks,
+                                   "gbs": 2 * nbytes / m / 1e6})
+    best = max(sweep_rows, key=lambda r: r["gbs"])
     del a, c
     torch.cuda.empty_cache()
-    return {"bytes": 2 * nbytes, "ms": ms, "gbs": 2 * nbytes / ms / 1e6}
+    return {"bytes": 2 * nbytes, "ms": ms, "gbs": 2 * nbytes / ms / 1e6,
+            "best": best, "sweep": sweep_rows}
 
 
 def adjoint_leg(torch, n=128, steps=400, k=20):
@@ -325,12 +389,12 @@ def cpu_leg(flags_np, seconds):
             f = O.step(f, 0.55, (1e-6, 0, 0), crop, n=chunk)
             dt += time.perf_counter() - t0
             nsteps += chunk
-        return nsteps, dt
+        return nsteps, dt, f
 
     threads = O.threads()
-    nsteps, dt = timed(seconds, 5)
+    nsteps, dt, f_end = timed(seconds, 5)
     O.set_threads(1)
-    n1, dt1 = timed(seconds / 4, 1)
+    n1, dt1, _ = timed(seconds / 4, 1)
     O.set_threads(threads)
     copy = O.host_copy_gbs()
     model_mflups = copy * 1e3 / 456
@@ -348,7 +412,39 @@ def cpu_leg(flags_np, seconds):
             "mflups": mflups, "one_thread_mlups": cells * n1 / dt1 / 1e6,
             "one_thread_sample": f"{n1} steps, {dt1:.1f} s", "host_cpu": model,
             "host_copy_gbs": copy, "model_mflups_456B": model_mflups,
-            "frac_of_model": mflups / model_mflups}
+            "frac_of_model": mflups / model_mflups,
+            "_state": (crop, nsteps + 1, f_end)}
+
+
+def crop_error_leg(torch, crop, nsteps, f_ref):
+    """The error against the FP64 oracle for every storage on the oracle's
+    own sample: the 128^3 crop run as its own periodic box (tau 0.55,
+    g_x 1e-6, from rest) for the same number of steps on the GPU; relative
+    L-inf over fluid cells of rho, u and delta-rho (the stricter measure:
+    normalised by max |rho - 1|), and the relative FP64 mass difference."""
+    from oracle import oracle as O
+    from paper_1112_0850_amd.lbm import LBM
+    F = (1e-6, 0.0, 0.0)
+    rho_r, u_r = O.macroscopics(f_ref, F, crop)
+    fl = (crop & 1) == 0
+    m_ref = O.reduce(f_ref, F, crop)[0]
+    out = {"workload": f"128^3 crop of the porous geometry as a periodic box, tau 0.55, g_x 1e-6, "
+                       f"from rest, {nsteps} steps (the oracle's CPU sample)"}
+    for st, s in (("f32", 0), ("f16", 12), ("bf16", 0), ("f64", 0), ("f32x", 0)):
+        sim = LBM(crop.shape, 0.55, F, st, flags=torch.from_numpy(crop).cuda(), f16_scale_log2=s)
+        sim.step(nsteps)
+        rho, u = sim.macroscopics(f64=True)
+        m = float(sim.reduce()[0].item())
+        rho, u = rho.cpu().numpy(), u.cpu().numpy()
+        out[st] = {"rho_rel_linf": float(abs(rho - rho_r)[fl].max() / abs(rho_r)[fl].max()),
+                   "u_rel_linf": float(abs(u - u_r)[:, fl].max() / abs(u_r)[:, fl].max()),
+                   "drho_rel_linf": float(abs(rho - rho_r)[fl].max() / abs(rho_r - 1)[fl].max()),
+                   "mass_rel_diff": abs(m - m_ref) / m_ref}
+        if st == "f16":
+            out[st]["f16_scale_log2"] = s
+        del sim
+    torch.cuda.empty_cache()
+    return out
 
 
 def gpu_clocks():
@@ -540,6 +636,8 @@ def trace_summary(trace_dir, bench_json):
 
 def main():
     args = parse()
+    if args.sweep_summary:
+        return sweep_summary(args.sweep_summary)
     if args.trace_summary:
         return trace_summary(*args.trace_summary)
     if args.profile_summary:
@@ -627,6 +725,8 @@ def main():
     if "cpu" in legs:
         log("cpu oracle sample")
         res["cpu"] = cpu_leg(flags, args.cpu_seconds)
+        log("error against the oracle on its sample, every storage")
+        res["error_vs_oracle"] = crop_error_leg(torch, *res["cpu"].pop("_state"))
 
     main_leg = res.get("f32") or next((res[k] for k in ("f16", "bf16", "f64", "f32x") if k in res),
                                       None)
@@ -682,10 +782,14 @@ def main():
         line["split_obstacle_kernel"] = res["split"]
     if "incomp" in res:
         line["incompressible_equilibrium"] = res["incomp"]
+    if "error_vs_oracle" in res:
+        line["error_vs_oracle"] = res["error_vs_oracle"]
     if "copy" in res:
         line["copy_gbs"] = res["copy"]["gbs"]
+        line["copy_best"] = res["copy"]["best"]
+        line["copy_sweep"] = res["copy"]["sweep"]
         if main_leg:
-            line["frac_of_copy_bw"] = main_leg["alg_gbs"] / res["copy"]["gbs"]
+            line["frac_of_copy_bw"] = main_leg["alg_gbs"] / res["copy"]["best"]["gbs"]
     if main_leg and "pull_copy" in main_leg:
         # the step's own access pattern without geometry or collision (lbm_pull_copy)
         line["pull_copy_probe"] = dict(main_leg["pull_copy"])

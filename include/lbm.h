@@ -39,15 +39,19 @@
  *    Every store rounds to nearest-even.  Collision arithmetic is FP32 for
  *    F32/F16/BF16 storage and FP64 for F64 and F32X storage.
  *    Solid cells carry no state of their own: every slot of a solid cell
- *    holds a marker (rewritten each step by the cell's own thread): a quiet
- *    NaN, or +infinity for a moving-wall cell when the wall velocity is not
- *    zero.  A pull that reads a marker takes the half-way bounce-back value
- *    from the pulling cell's own opposite slot instead, plus the moving-wall
- *    term 6 w_i (c_i . u_w) in storage units for an infinity marker.
+ *    holds a marker (rewritten each step by the cell's own thread), one of
+ *    two fixed quiet-NaN bit patterns of the storage type (LBM_MARK_* below,
+ *    also returned by lbm_solid_markers): the moving-wall marker for a
+ *    moving-wall cell when the wall velocity is not zero, else the resting
+ *    one.  A pull whose raw bits equal a marker takes the half-way
+ *    bounce-back value from the pulling cell's own opposite slot instead,
+ *    plus the moving-wall term 6 w_i (c_i . u_w) in storage units for the
+ *    moving-wall marker.  Any other value is data: a NaN or infinity that
+ *    arises in a fluid cell (a 16-bit overflow, corrupted input) enters the
+ *    neighbours' collisions and so reaches lbm_reduce as a non-finite sum.
  *    Padding stays 0.  The library maintains the markers itself (init, step,
  *    save/restore); after writing a grid from outside, call
- *    lbm_refresh_solids.  Fluid values must never be NaN (nor infinite
- *    when the wall velocity is not zero).
+ *    lbm_refresh_solids.  Fluid values must never carry a marker pattern.
  *  - Scalar fields are [nz][ny][nx], vector fields [3][nz][ny][nx] (no
  *    padding).  flags are uint8 [nz][ny][nx]: bit0 LBM_FLAG_SOLID (obstacle
  *    cell, never read or written), bit1 LBM_FLAG_NOFORCE (fluid cell without
@@ -112,6 +116,17 @@ typedef enum {
 
 enum { LBM_FLAG_SOLID = 1, LBM_FLAG_NOFORCE = 2, LBM_FLAG_MOVING = 4 };
 
+/* Solid-cell markers: raw bits of a stored element (sign set, quiet NaN,
+ * fixed payload; the moving-wall marker is the resting one with bit 0 set). */
+#define LBM_MARK_F32_REST 0xFFD0D0D0u /* LBM_F32 and LBM_F32X */
+#define LBM_MARK_F32_MOVING 0xFFD0D0D1u
+#define LBM_MARK_F64_REST 0xFFFD0D0D0D0D0D0Cull
+#define LBM_MARK_F64_MOVING 0xFFFD0D0D0D0D0D0Dull
+#define LBM_MARK_F16_REST 0xFED4u
+#define LBM_MARK_F16_MOVING 0xFED5u
+#define LBM_MARK_BF16_REST 0xFFD4u
+#define LBM_MARK_BF16_MOVING 0xFFD5u
+
 typedef struct {
   int32_t nx, ny, nz;     /* cells per axis, each >= 1 */
   int32_t storage;        /* lbm_storage */
@@ -153,8 +168,16 @@ lbm_status lbm_query(const lbm_params* p, int64_t* x_stride, int64_t* dir_stride
 int32_t lbm_bytes_per_update(int32_t storage);
 
 /* Copies the D3Q19 tables in the interface order above: e[19][3], w[19],
- * opp[19] (any pointer may be NULL).  Host memory; needs no GPU. */
+ * opp[19] (any pointer may be NULL).  Host memory; needs no GPU.  The set
+ * is the 19-velocity lattice of Sec. 2 with the weights of Qian et al.
+ * (1992), which the paper's equilibrium defers to. */
 void lbm_lattice(int32_t* e, double* w, int32_t* opp);
+
+/* Raw bits of the resting and the moving-wall solid marker of a storage
+ * type (the LBM_MARK_* values; zero-extended for 16- and 32-bit types).
+ * Host only.  Errors: LBM_E_ARG for an unknown storage type or a NULL
+ * output. */
+lbm_status lbm_solid_markers(int32_t storage, uint64_t* rest, uint64_t* moving);
 
 /* Creates a context over caller-owned memory and enqueues the initial state
  * f*(0) = f^eq(rho0, u0) (Sec. 2 step 2 equilibrium) on fluid cells of
@@ -270,6 +293,16 @@ lbm_status lbm_adjoint_finish_dF(lbm_ctx* ctx, const double* dLdF_partials, doub
  * pointers 256-byte aligned, n_bytes a multiple of 16. */
 lbm_status lbm_stream_copy(void* c, const void* a, size_t n_bytes, void* stream);
 
+/* Variants of the copy for the attainable-bandwidth sweep (the paper finds
+ * the sustainable bandwidth by sweeping its STREAM copy over launch shapes,
+ * Sec. 3): vec_per_thread in {1, 2, 4} 16-byte elements per thread per pass,
+ * nontemporal = 1 for non-temporal loads and stores, blocks = the number of
+ * 256-thread blocks striding through the array (0 or more than one pass
+ * needs: exactly one pass).  Pointers and n_bytes as for lbm_stream_copy.
+ * Errors: LBM_E_ARG, LBM_E_HIP. */
+lbm_status lbm_copy_probe(void* c, const void* a, size_t n_bytes, int32_t vec_per_thread,
+                          int32_t nontemporal, int32_t blocks, void* stream);
+
 /* The same model with the access pattern of the step itself: one pure
  * streaming pass dst_i(x) = src_i(x - c_i) over the context's grid layout
  * (periodic in every axis; flags, walls and collision ignored), launched
@@ -282,13 +315,15 @@ lbm_status lbm_pull_copy(lbm_ctx* ctx, const void* src, void* dst);
 
 /* Launch-bound runs (small grids): with steps_per_graph = G (even, 2..4096)
  * lbm_step replays HIP graphs of G captured steps on the context's stream
- * (one graph per starting grid, captured on first use on a library-owned
- * stream; only the step kernels are recorded) and launches the remaining
- * n mod G steps one by one; results are bit-identical to plain launches.
- * 0 (the default) launches every step.  The HIP runtime owns the graphs'
- * resources; changing G or destroying the context waits for the latest
- * replay (on the stream it was queued on, also after lbm_set_stream) and
- * releases them.  Errors: LBM_E_ARG, LBM_E_HIP. */
+ * and launches the remaining n mod G steps one by one; results are
+ * bit-identical to plain launches.  This call captures the two graphs (one
+ * per starting grid, on a library-owned stream; only the step kernels are
+ * recorded) and instantiates them, so lbm_step itself only enqueues.  The
+ * HIP runtime owns the graphs' resources.  Changing G (0 turns replays off,
+ * the default) or destroying the context first waits on the host for the
+ * latest replay -- through an event recorded after it, so also after
+ * lbm_set_stream and after the caller destroyed the stream it ran on -- and
+ * releases the old graphs.  Errors: LBM_E_ARG, LBM_E_HIP (graphs off). */
 lbm_status lbm_use_graphs(lbm_ctx* ctx, int32_t steps_per_graph);
 
 /* Destroys a context: its host memory and, if graphs were used, the graphs

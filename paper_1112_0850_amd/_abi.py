@@ -40,6 +40,7 @@ _SIGNATURES = {
                         C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "lbm_bytes_per_update": (C.c_int32, [C.c_int32]),
     "lbm_lattice": (None, [C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "lbm_solid_markers": (_st, [C.c_int32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
     "lbm_init": (_st, [C.POINTER(_vp), C.POINTER(lbm_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "lbm_step": (_st, [_vp, C.c_int32]),
     "lbm_step_from": (_st, [_vp, _vp, _vp]),
@@ -58,6 +59,7 @@ _SIGNATURES = {
     "lbm_adjoint_init": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_adjoint_finish_dF": (_st, [_vp, _vp, _vp]),
     "lbm_stream_copy": (_st, [_vp, _vp, C.c_size_t, _vp]),
+    "lbm_copy_probe": (_st, [_vp, _vp, C.c_size_t, C.c_int32, C.c_int32, C.c_int32, _vp]),
     "lbm_pull_copy": (_st, [_vp, _vp, _vp]),
     "lbm_use_graphs": (_st, [_vp, C.c_int32]),
     "lbm_destroy": (None, [_vp]),
@@ -128,6 +130,13 @@ def lbm_lattice():
     opp = (C.c_int32 * 19)()
     lib().lbm_lattice(e, w, opp)
     return [tuple(e[3 * i:3 * i + 3]) for i in range(19)], list(w), list(opp)
+
+
+def lbm_solid_markers(storage):
+    """(resting, moving-wall) marker bits of a storage type."""
+    r, m = C.c_uint64(), C.c_uint64()
+    check(lib().lbm_solid_markers(int(storage), C.byref(r), C.byref(m)))
+    return r.value, m.value
 
 
 def lbm_init(p, grid_a, grid_b, flags, scratch, rho0, u0, stream):
@@ -203,6 +212,11 @@ def lbm_adjoint_finish_dF(ctx, partials, dLdF3):
 
 def lbm_stream_copy(dst, src, n_bytes, stream):
     check(lib().lbm_stream_copy(dst, src, int(n_bytes), stream))
+
+
+def lbm_copy_probe(dst, src, n_bytes, vec_per_thread, nontemporal, blocks, stream):
+    check(lib().lbm_copy_probe(dst, src, int(n_bytes), int(vec_per_thread), int(nontemporal),
+                               int(blocks), stream))
 
 
 def lbm_pull_copy(ctx, src, dst):

@@ -1,7 +1,10 @@
 // abi.hip -- the extern "C" boundary declared in include/lbm.h: argument
 // validation on the host, context bookkeeping (which lattice holds f*(t)),
 // and dispatch to the kernel launchers.  Nothing here allocates device
-// memory or synchronises.
+// memory, and the stepping, field and adjoint calls only enqueue work.  Two
+// calls wait on the host: lbm_use_graphs (which also captures and
+// instantiates the replayed step graphs) and lbm_destroy, both for the
+// latest graph replay, through an event recorded after it.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -13,6 +16,18 @@
 #include "../../include/lbm.h"
 #include "d3q19.h"
 #include "kernels.h"
+
+static_assert(lbm::Storage<lbm::ST_F32>::kRest == LBM_MARK_F32_REST &&
+                  lbm::Storage<lbm::ST_F32>::kMoving == LBM_MARK_F32_MOVING &&
+                  lbm::Storage<lbm::ST_F32X>::kRest == LBM_MARK_F32_REST &&
+                  lbm::Storage<lbm::ST_F32X>::kMoving == LBM_MARK_F32_MOVING &&
+                  lbm::Storage<lbm::ST_F64>::kRest == LBM_MARK_F64_REST &&
+                  lbm::Storage<lbm::ST_F64>::kMoving == LBM_MARK_F64_MOVING &&
+                  lbm::Storage<lbm::ST_F16>::kRest == LBM_MARK_F16_REST &&
+                  lbm::Storage<lbm::ST_F16>::kMoving == LBM_MARK_F16_MOVING &&
+                  lbm::Storage<lbm::ST_BF16>::kRest == LBM_MARK_BF16_REST &&
+                  lbm::Storage<lbm::ST_BF16>::kMoving == LBM_MARK_BF16_MOVING,
+              "solid markers of the kernels and of lbm.h differ");
 
 namespace {
 
@@ -116,9 +131,10 @@ struct lbm_ctx {
   int64_t t;
   bool force;
   int32_t graph_steps;         // 0: one launch per step; else replay graphs of this many steps
-  hipGraphExec_t graph[2];     // per starting grid, captured on first use
+  hipGraphExec_t graph[2];     // per starting grid, captured by lbm_use_graphs
   hipStream_t capture_stream;  // library-owned, used only to capture the graphs
-  hipStream_t replay_stream;   // stream of the latest graph replay (may predate lbm_set_stream)
+  hipEvent_t replay_done;      // recorded after the latest graph replay
+  bool replayed;               // replay_done has been recorded
 };
 
 namespace {
@@ -144,13 +160,13 @@ lbm_status launch_steps(lbm_ctx* c, const void* src, void* dst) {
   return launch_steps_on(c, src, dst, c->stream);
 }
 
-// Waits for the latest replay (on whatever stream it was queued), then
-// destroys the executable graphs.
+// Waits for the latest replay (through its event, valid whatever became of
+// the stream it was queued on), then destroys the executable graphs.
 hipError_t drop_graphs(lbm_ctx* c) {
   hipError_t e = hipSuccess;
-  if (c->replay_stream) {
-    e = hipStreamSynchronize(c->replay_stream);
-    c->replay_stream = nullptr;
+  if (c->replayed) {
+    e = hipEventSynchronize(c->replay_done);
+    c->replayed = false;
   }
   for (int p = 0; p < 2; ++p)
     if (c->graph[p]) {
@@ -227,6 +243,19 @@ void lbm_lattice(int32_t* e, double* w, int32_t* opp) {
   }
 }
 
+lbm_status lbm_solid_markers(int32_t storage, uint64_t* rest, uint64_t* moving) {
+  if (!rest || !moving) return fail(LBM_E_ARG, "rest and moving must not be NULL");
+  switch (storage) {
+    case LBM_F32:
+    case LBM_F32X: *rest = LBM_MARK_F32_REST; *moving = LBM_MARK_F32_MOVING; break;
+    case LBM_F64: *rest = LBM_MARK_F64_REST; *moving = LBM_MARK_F64_MOVING; break;
+    case LBM_F16: *rest = LBM_MARK_F16_REST; *moving = LBM_MARK_F16_MOVING; break;
+    case LBM_BF16: *rest = LBM_MARK_BF16_REST; *moving = LBM_MARK_BF16_MOVING; break;
+    default: return fail(LBM_E_ARG, "unknown storage type %d", storage);
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* grid_a, void* grid_b,
                     const uint8_t* flags, void* scratch, const float* rho0, const float* u0,
                     void* stream) {
@@ -267,7 +296,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* grid_a, void* grid
   c->graph_steps = 0;
   c->graph[0] = c->graph[1] = nullptr;
   c->capture_stream = nullptr;
-  c->replay_stream = nullptr;
+  c->replay_done = nullptr;
+  c->replayed = false;
   hipError_t e = lbm::launch_fill_zero(grid_a, sz.grid_bytes, c->stream);
   if (e == hipSuccess) e = lbm::launch_fill_zero(grid_b, sz.grid_bytes, c->stream);
   if (e == hipSuccess)
@@ -284,16 +314,18 @@ lbm_status lbm_step(lbm_ctx* c, int32_t n) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
   if (n < 0) return fail(LBM_E_ARG, "step count must be >= 0 (got %d)", n);
+  bool replay = false;
   while (c->graph_steps && n >= c->graph_steps) {
-    if (!c->graph[c->cur]) {
-      st = build_graph(c, c->cur);
-      if (st != LBM_OK) return st;
-    }
     hipError_t e = hipGraphLaunch(c->graph[c->cur], c->stream);
     if (e != hipSuccess) return hip_fail(e, "graph launch");
-    c->replay_stream = c->stream;
+    replay = true;
     n -= c->graph_steps;
     c->t += c->graph_steps;
+  }
+  if (replay) {
+    hipError_t e = hipEventRecord(c->replay_done, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "replay event");
+    c->replayed = true;
   }
   for (int32_t k = 0; k < n; ++k) {
     st = launch_steps(c, c->grid[c->cur], c->grid[c->cur ^ 1]);
@@ -447,6 +479,21 @@ lbm_status lbm_stream_copy(void* dst, const void* src, size_t n_bytes, void* str
   return e == hipSuccess ? LBM_OK : hip_fail(e, "copy launch");
 }
 
+lbm_status lbm_copy_probe(void* dst, const void* src, size_t n_bytes, int32_t vec_per_thread,
+                          int32_t nontemporal, int32_t blocks, void* stream) {
+  if (!dst || !src) return fail(LBM_E_ARG, "copy pointers must not be NULL");
+  if (!aligned256(dst) || !aligned256(src)) return fail(LBM_E_ARG, "copy pointers must be 256-byte aligned");
+  if (n_bytes % 16) return fail(LBM_E_ARG, "n_bytes must be a multiple of 16");
+  if (vec_per_thread != 1 && vec_per_thread != 2 && vec_per_thread != 4)
+    return fail(LBM_E_ARG, "vec_per_thread must be 1, 2 or 4 (got %d)", vec_per_thread);
+  if (nontemporal != 0 && nontemporal != 1) return fail(LBM_E_ARG, "nontemporal must be 0 or 1");
+  if (blocks < 0) return fail(LBM_E_ARG, "blocks must be >= 0 (got %d)", blocks);
+  if (!n_bytes) return LBM_OK;
+  hipError_t e = lbm::launch_copy_variant(dst, src, n_bytes / 16, vec_per_thread, nontemporal != 0,
+                                          size_t(blocks), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "copy probe launch");
+}
+
 lbm_status lbm_pull_copy(lbm_ctx* c, const void* src, void* dst) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;
@@ -463,18 +510,36 @@ lbm_status lbm_use_graphs(lbm_ctx* c, int32_t steps_per_graph) {
   if (steps_per_graph != 0 && (steps_per_graph < 2 || steps_per_graph > 4096 || steps_per_graph % 2))
     return fail(LBM_E_ARG, "steps_per_graph must be 0 or an even count in [2, 4096] (got %d)",
                 steps_per_graph);
-  if (steps_per_graph != c->graph_steps) {
-    hipError_t e = drop_graphs(c);  // no replay of the old graphs left in flight
-    if (e != hipSuccess) return hip_fail(e, "stream synchronize");
-    c->graph_steps = steps_per_graph;
+  if (steps_per_graph == c->graph_steps) return LBM_OK;
+  hipError_t e = drop_graphs(c);  // no replay of the old graphs left in flight
+  if (e != hipSuccess) return hip_fail(e, "waiting for the latest graph replay");
+  c->graph_steps = 0;
+  if (!steps_per_graph) return LBM_OK;
+  if (!c->capture_stream) {
+    e = hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "capture stream");
   }
-  return LBM_OK;
+  if (!c->replay_done) {
+    e = hipEventCreateWithFlags(&c->replay_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      c->replay_done = nullptr;
+      return hip_fail(e, "replay event");
+    }
+  }
+  c->graph_steps = steps_per_graph;
+  for (int p = 0; p < 2 && st == LBM_OK; ++p) st = build_graph(c, p);
+  if (st != LBM_OK) {
+    (void)drop_graphs(c);
+    c->graph_steps = 0;
+  }
+  return st;
 }
 
 void lbm_destroy(lbm_ctx* c) {
   if (!c) return;
   (void)drop_graphs(c);
   if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
+  if (c->replay_done) (void)hipEventDestroy(c->replay_done);
   delete c;
 }
 

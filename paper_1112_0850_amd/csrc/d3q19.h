@@ -77,7 +77,13 @@ constexpr uint8_t FLAG_NOFORCE = 2;
 constexpr uint8_t FLAG_MOVING = 4;  // with FLAG_SOLID: a wall cell moving with the wall velocity
 
 // Storage formats of the population offset g = f - w.  `load` widens a stored
-// element to the compute type, `store` rounds to nearest-even.
+// element to the compute type, `store` rounds to nearest-even.  U is the raw
+// bit type of a stored element; kRest and kMoving are the two solid-cell
+// markers of the format: quiet NaNs with the sign bit set and a fixed
+// payload, which neither arithmetic (its NaNs are the default positive NaN
+// or a propagated input) nor overflow (infinity) produces.  The kernels
+// compare raw bits against them, so a NaN or infinity that arises in a fluid
+// cell is not mistaken for a wall and propagates.  kMoving = kRest | 1.
 enum StorageKind { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2, ST_F64 = 3, ST_F32X = 4 };
 
 template <int K>
@@ -87,6 +93,8 @@ template <>
 struct Storage<ST_F32> {
   using T = float;
   using C = float;
+  using U = uint32_t;
+  static constexpr U kRest = 0xFFD0D0D0u, kMoving = 0xFFD0D0D1u;
   __device__ static C load(T v, C) { return v; }
   __device__ static T store(C v, C) { return v; }
 };
@@ -96,6 +104,8 @@ template <>
 struct Storage<ST_F32X> {
   using T = float;
   using C = double;
+  using U = uint32_t;
+  static constexpr U kRest = 0xFFD0D0D0u, kMoving = 0xFFD0D0D1u;
   __device__ static C load(T v, C) { return v; }
   __device__ static T store(C v, C) { return T(v); }
 };
@@ -104,6 +114,8 @@ template <>
 struct Storage<ST_F64> {
   using T = double;
   using C = double;
+  using U = uint64_t;
+  static constexpr U kRest = 0xFFFD0D0D0D0D0D0Cull, kMoving = 0xFFFD0D0D0D0D0D0Dull;
   __device__ static C load(T v, C) { return v; }
   __device__ static T store(C v, C) { return v; }
 };
@@ -115,6 +127,8 @@ template <>
 struct Storage<ST_F16> {
   using T = _Float16;
   using C = float;
+  using U = uint16_t;
+  static constexpr U kRest = 0xFED4u, kMoving = 0xFED5u;
   __device__ static C load(T v, C inv_scale) { return float(v) * inv_scale; }
   __device__ static T store(C v, C scale) { return T(v * scale); }
 };
@@ -125,8 +139,20 @@ template <>
 struct Storage<ST_BF16> {
   using T = __bf16;
   using C = float;
+  using U = uint16_t;
+  static constexpr U kRest = 0xFFD4u, kMoving = 0xFFD5u;
   __device__ static C load(T v, C) { return float(v); }
   __device__ static T store(C v, C) { return T(v); }
 };
+
+// Raw bits of a stored element and back.
+template <int K>
+__device__ __forceinline__ typename Storage<K>::U raw_bits(typename Storage<K>::T v) {
+  return __builtin_bit_cast(typename Storage<K>::U, v);
+}
+template <int K>
+__device__ __forceinline__ typename Storage<K>::T from_bits(typename Storage<K>::U u) {
+  return __builtin_bit_cast(typename Storage<K>::T, u);
+}
 
 }  // namespace lbm

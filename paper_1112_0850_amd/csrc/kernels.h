@@ -61,6 +61,10 @@ hipError_t launch_adj_init(const Geo& g, const PhysParams& ph, const uint8_t* fl
                            const float* rho0, const float* u0, float* dL_du0, hipStream_t s);
 hipError_t launch_adj_finish(const Geo& g, const double* partials, double* out3, hipStream_t s);
 hipError_t launch_copy(void* c, const void* a, size_t n16, hipStream_t s);
+// Copy variants for the bandwidth sweep: vec in {1, 2, 4} 16-byte elements per
+// thread, non-temporal or not, `blocks` blocks (0 = one pass over the array).
+hipError_t launch_copy_variant(void* c, const void* a, size_t n16, int vec, bool nt, size_t blocks,
+                               hipStream_t s);
 // Pull-copy probe: one pure-streaming pass dst_i(x) = src_i(x - c_i) (periodic,
 // no geometry, no collision) with the step kernel's launch and access pattern.
 hipError_t launch_pull_copy(int storage, const Geo& g, const void* src, void* dst, hipStream_t s);

@@ -75,11 +75,11 @@ static Phys<C> to_phys(const PhysParams& p) {
   return r;
 }
 
-// Marker of a solid cell: a quiet NaN, or +infinity for a moving-wall cell
-// while moving-wall markers are in use.
-template <typename C>
-__device__ __forceinline__ C solid_marker(uint8_t fl, bool moving) {
-  return (moving && (fl & FLAG_MOVING)) ? C(__builtin_inf()) : C(__builtin_nan(""));
+// Marker of a solid cell in storage format K: the moving-wall marker for a
+// moving-wall cell while moving-wall markers are in use, else the resting one.
+template <int K>
+__device__ __forceinline__ typename Storage<K>::T solid_marker(uint8_t fl, bool moving) {
+  return from_bits<K>((moving && (fl & FLAG_MOVING)) ? Storage<K>::kMoving : Storage<K>::kRest);
 }
 
 // ---------------------------------------------------------------------------
@@ -450,10 +450,13 @@ __device__ __forceinline__ float fp32_result(float v) {
   return v;
 }
 
-template <int WALLS, typename C>
-__device__ __forceinline__ bool is_marker(C v) {
-  if (WALLS == 2) return !__builtin_isfinite(v);  // NaN or infinity
-  return v != v;                                   // NaN
+// A pulled element is a solid marker when its raw bits are one of the two
+// marker patterns (WALLS = 2) or the resting one (WALLS = 1); any other
+// value -- a NaN or infinity that arose in a fluid cell included -- is data.
+template <int K, int WALLS>
+__device__ __forceinline__ bool is_marker(typename Storage<K>::U r) {
+  if (WALLS == 2) return (r | 1u) == Storage<K>::kMoving;  // kMoving = kRest | 1
+  return r == Storage<K>::kRest;
 }
 
 // Cells per lane of the step kernel: a wave owns a run of 64*M cells of one
@@ -515,10 +518,17 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
   for (int m = 0; m < M; ++m) fl[m] = SOLIDS ? flags[n[m].fown] : uint8_t(0);
   const size_t pb = size_t(g.plane) * sizeof(T);
   C f[M][Q];
+  bool mark[M][Q];  // the pull returned a solid marker (raw-bit test at the load)
+  bool mov[M][Q];   // ... the moving-wall marker
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[m][i] = C(*elem_rx(src, pb, i, src_row(n[m], i), src_x(n[m], i)));
+    for (int i = 0; i < Q; ++i) {
+      const T v = *elem_rx(src, pb, i, src_row(n[m], i), src_x(n[m], i));
+      mark[m][i] = MARKERS && i != 0 && is_marker<K, WALLS>(raw_bits<K>(v));
+      mov[m][i] = WALLS == 2 && i != 0 && raw_bits<K>(v) == Storage<K>::kMoving;
+      f[m][i] = C(v);
+    }
   bool solid[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
@@ -526,9 +536,9 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
     if (MARKERS) {
 #pragma unroll
       for (int i = 1; i < Q; ++i)
-        if (is_marker<WALLS>(f[m][i]) && !solid[m]) {
+        if (mark[m][i] && !solid[m]) {
           C b = C(*elem_rx(src, pb, D3Q19::opp[i], n[m].row[1][1], n[m].xn[1]));
-          if (WALLS == 2 && __builtin_isinf(f[m][i])) b += k.Kw[i];
+          if (WALLS == 2 && mov[m][i]) b += k.Kw[i];
           f[m][i] = b;
         }
     }
@@ -542,13 +552,13 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
     } else {
       collide<C, FORCE, SCALED, INC, K == ST_F32>(f[m], k, C(1));
     }
-    const C marker = solid_marker<C>(fl[m], WALLS == 2 || (WALLS == 3 && k.moving));
+    const T marker = solid_marker<K>(fl[m], WALLS == 2 || (WALLS == 3 && k.moving));
     if (valid[m]) {
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        C out = solid[m] ? marker : f[m][i];
+        C out = f[m][i];
         if constexpr (K == ST_F16) out = fp32_result(out);
-        stream_store(elem_rx(dst, pb, i, n[m].row[1][1], n[m].xn[1]), T(out));
+        stream_store(elem_rx(dst, pb, i, n[m].row[1][1], n[m].xn[1]), solid[m] ? marker : T(out));
       }
     }
   }
@@ -590,14 +600,13 @@ __global__ __launch_bounds__(kBlock) void k_mark_solids(typename Storage<K>::T* 
                                                         const uint8_t* __restrict__ flags, Geo g,
                                                         int moving) {
   using T = typename Storage<K>::T;
-  using C = typename Storage<K>::C;
   const Loc l = locate(g);
   if (!l.valid) return;
   const Nbhd n = neighbourhood(g, l);
   const uint8_t fl = flags[n.fown];
   if (!(fl & FLAG_SOLID)) return;
   const size_t pb = size_t(g.plane) * sizeof(T);
-  const T marker = T(solid_marker<C>(fl, moving != 0));
+  const T marker = solid_marker<K>(fl, moving != 0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) *elem(grid, pb, i, n.own) = marker;
 }
@@ -619,7 +628,7 @@ __global__ __launch_bounds__(kBlock) void k_init(typename Storage<K>::T* __restr
   const uint32_t c = n.fown;
   const size_t pb = size_t(g.plane) * sizeof(T);
   if (flags && (flags[c] & FLAG_SOLID)) {  // solid marker
-    const T marker = T(solid_marker<C>(flags[c], ph.moving != 0));
+    const T marker = solid_marker<K>(flags[c], ph.moving != 0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) *elem(grid, pb, i, n.own) = marker;
     return;
@@ -1008,6 +1017,34 @@ __global__ __launch_bounds__(kBlock) void k_copy(uint4* __restrict__ c, const ui
   if (i < n16) c[i] = a[i];
 }
 
+// The copy's variants for the attainable-bandwidth sweep: V 16-byte elements
+// per thread per pass (a wave moves V consecutive 1 KiB runs), optionally
+// with non-temporal loads and stores, over a grid of `blocks` blocks that
+// strides through the array (blocks large enough for one pass = no stride).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int V, bool NT>
+__global__ __launch_bounds__(kBlock) void k_copy_v(u32x4* __restrict__ c, const u32x4* __restrict__ a,
+                                                   size_t n16) {
+  const size_t stride = size_t(gridDim.x) * kBlock * V;
+  for (size_t base = size_t(blockIdx.x) * kBlock * V + threadIdx.x; base < n16; base += stride) {
+    u32x4 v[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const size_t i = base + size_t(k) * kBlock;
+      if (i < n16) v[k] = NT ? __builtin_nontemporal_load(a + i) : a[i];
+    }
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const size_t i = base + size_t(k) * kBlock;
+      if (i < n16) {
+        if (NT) __builtin_nontemporal_store(v[k], c + i);
+        else c[i] = v[k];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
@@ -1298,6 +1335,28 @@ hipError_t launch_copy(void* c, const void* a, size_t n16, hipStream_t s) {
   const size_t blocks = (n16 + kBlock - 1) / kBlock;
   hipLaunchKernelGGL(k_copy, dim3(unsigned(blocks)), dim3(kBlock), 0, s,
                      reinterpret_cast<uint4*>(c), reinterpret_cast<const uint4*>(a), n16);
+  return hipGetLastError();
+}
+
+template <int V, bool NT>
+static void copy_v(void* c, const void* a, size_t n16, size_t blocks, hipStream_t s) {
+  const size_t full = (n16 + size_t(kBlock) * V - 1) / (size_t(kBlock) * V);
+  const size_t b = (blocks == 0 || blocks > full) ? full : blocks;
+  hipLaunchKernelGGL((k_copy_v<V, NT>), dim3(unsigned(b)), dim3(kBlock), 0, s,
+                     reinterpret_cast<u32x4*>(c), reinterpret_cast<const u32x4*>(a), n16);
+}
+
+hipError_t launch_copy_variant(void* c, const void* a, size_t n16, int vec, bool nt, size_t blocks,
+                               hipStream_t s) {
+  switch (vec * 2 + (nt ? 1 : 0)) {
+    case 2: copy_v<1, false>(c, a, n16, blocks, s); break;
+    case 3: copy_v<1, true>(c, a, n16, blocks, s); break;
+    case 4: copy_v<2, false>(c, a, n16, blocks, s); break;
+    case 5: copy_v<2, true>(c, a, n16, blocks, s); break;
+    case 8: copy_v<4, false>(c, a, n16, blocks, s); break;
+    case 9: copy_v<4, true>(c, a, n16, blocks, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -180,6 +180,17 @@ def stream_copy(dst, src, stream=None):
                       src.numel() * src.element_size(), ctypes.c_void_p(s.cuda_stream))
 
 
+def copy_probe(dst, src, vec_per_thread=1, nontemporal=False, blocks=0, stream=None):
+    """A variant of the copy dst = src for the bandwidth sweep (16-byte
+    elements per thread, non-temporal accesses, grid-stride block count)."""
+    if dst.numel() * dst.element_size() != src.numel() * src.element_size():
+        raise ValueError("size mismatch")
+    s = torch.cuda.current_stream() if stream is None else stream
+    A.lbm_copy_probe(_ptr(_aligned(dst, "dst")), _ptr(_aligned(src, "src")),
+                     src.numel() * src.element_size(), vec_per_thread, int(bool(nontemporal)),
+                     blocks, ctypes.c_void_p(s.cuda_stream))
+
+
 class _Rollout(torch.autograd.Function):
     """(rho_T, u_T) after `steps` updates from f*(0) = f^eq(1, u0) under the
     body force g; backward runs the hand-written adjoint kernels with forward

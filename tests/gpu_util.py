@@ -50,15 +50,33 @@ def f_to_grid(sim, f, offsets=False, flags=None):
     torch.cuda.synchronize()
 
 
+_INT = {0: (torch.int32, np.uint32), 1: (torch.int16, np.uint16), 2: (torch.int16, np.uint16),
+        3: (torch.int64, np.uint64), 4: (torch.int32, np.uint32)}
+
+
+def raw_bits(sim, grid=None):
+    """The stored bit patterns of a grid (default: current) as unsigned
+    integers [19, nz, ny, nx] -- NaN payloads survive, unlike a float view."""
+    buf = sim.grids[sim.current] if grid is None else grid
+    it, ut = _INT[sim.storage]
+    nx = sim.shape[2]
+    return sim.grid_view(buf, dtype=it)[..., :nx].cpu().numpy().view(ut)
+
+
 def check_solids(sim, flags, grid=None):
-    """Every slot of every solid cell holds its marker (NaN; +infinity for a
-    moving-wall cell when the wall velocity is not zero); returns the offsets
-    with solid cells zeroed (the oracle's convention)."""
-    g = grid_to_f(sim, grid, offsets=True, raw=True)
+    """Every slot of every solid cell holds its marker bits (the moving-wall
+    marker for a moving-wall cell when the wall velocity is not zero, else
+    the resting one) and no fluid slot does; fluid values are finite.
+    Returns the offsets with solid cells zeroed (the oracle's convention)."""
+    from paper_1112_0850_amd import _abi as A
+    rest, mov = A.lbm_solid_markers(sim.storage)
+    bits = raw_bits(sim, grid)
     solid = (flags & 1) == 1
     moving = solid & ((flags & 4) == 4) & any(v != 0.0 for v in sim.wall_u)
-    assert np.isnan(g[:, solid & ~moving]).all(), "solid marker missing"
-    assert (g[:, moving] == np.inf).all(), "moving-wall marker missing"
+    assert (bits[:, solid & ~moving] == rest).all(), "solid marker missing"
+    assert (bits[:, moving] == mov).all(), "moving-wall marker missing"
+    assert not np.isin(bits[:, ~solid], [rest, mov]).any(), "marker in a fluid slot"
+    g = grid_to_f(sim, grid, offsets=True, raw=True)
     assert np.isfinite(g[:, ~solid]).all(), "non-finite fluid population"
     g[:, solid] = 0.0
     return g

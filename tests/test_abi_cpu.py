@@ -157,3 +157,43 @@ def test_missing_library_fails_loudly(tmp_path, monkeypatch):
         A.lib()
     with pytest.raises(ImportError):
         A.lbm_query(A.params((4, 4, 4), 0.7))
+
+
+def _header_define(name):
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    m = re.search(rf"#define {name} (0x[0-9A-Fa-f]+)u?l?l?", src)
+    return int(m.group(1), 16)
+
+
+@pytest.mark.parametrize("storage,bits,expo,quiet", [
+    (A.LBM_F32, 32, 8, 22), (A.LBM_F32X, 32, 8, 22), (A.LBM_F64, 64, 11, 51),
+    (A.LBM_F16, 16, 5, 9), (A.LBM_BF16, 16, 8, 6)])
+def test_solid_markers_are_reserved_quiet_nans(storage, bits, expo, quiet):
+    """Each marker is a quiet NaN of its format with the sign bit set and a
+    non-zero payload beyond the quiet bit -- neither the default NaN of
+    arithmetic (positive, empty payload) nor an infinity -- the two differ in
+    bit 0 only, and they are the values the header defines."""
+    rest, mov = A.lbm_solid_markers(storage)
+    assert mov == rest | 1 and rest & 1 == 0
+    mant = bits - 1 - expo
+    for v in (rest, mov):
+        assert v >> (bits - 1) == 1                               # sign
+        assert (v >> mant) & ((1 << expo) - 1) == (1 << expo) - 1  # all-ones exponent
+        assert (v >> quiet) & 1 == 1                               # quiet NaN
+        assert v & ((1 << quiet) - 1) != 0                         # payload
+    name = {A.LBM_F32: "F32", A.LBM_F32X: "F32", A.LBM_F64: "F64", A.LBM_F16: "F16",
+            A.LBM_BF16: "BF16"}[storage]
+    assert rest == _header_define(f"LBM_MARK_{name}_REST")
+    assert mov == _header_define(f"LBM_MARK_{name}_MOVING")
+    with pytest.raises(A.LBMError):
+        A.lbm_solid_markers(9)
+
+
+def test_copy_probe_argument_errors():
+    a, c = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    for args in [(c, a, 17, 1, 0, 0), (c, a, 64, 3, 0, 0), (c, a, 64, 1, 2, 0),
+                 (c, a, 64, 1, 0, -1), (ctypes.c_void_p(0x20010), a, 64, 1, 0, 0), (None, a, 64, 1, 0, 0)]:
+        with pytest.raises(A.LBMError) as e:
+            A.lbm_copy_probe(*args, None)
+        assert e.value.status == A.LBM_E_ARG
+    A.lbm_copy_probe(c, a, 0, 4, 1, 0, None)  # nothing to copy: no launch

@@ -135,11 +135,12 @@ def test_rollout_gradient_vs_oracle_adjoint():
 
 
 def test_rollout_gradient_vs_central_differences():
-    """Periodic 32^3, smooth u0 (amplitude 0.02), g = (1e-6, 0, 0), tau = 0.6,
-    200 steps, k = 20: directional derivatives along 4 smooth directions and
-    each force component against FP64 central differences of the oracle
-    (eps = 1e-4 on u0, 1e-6 on g); bar 1e-4 relative."""
-    n, tau, steps = 32, 0.6, 200
+    """Periodic 32^3 copy of the differentiable workload: smooth u0
+    (amplitude 0.02), g = (1e-6, 0, 0), tau = 0.6, its 400 steps, k = 20:
+    directional derivatives along 4 smooth directions and each force
+    component against FP64 central differences of the oracle (eps = 1e-4 on
+    u0, 1e-6 on g); bar 1e-4 relative."""
+    n, tau, steps = 32, 0.6, 400
     say("rollout gradient vs central differences, 32^3", steps, "steps")
     u0 = _f32(I.smooth_field(n, 2024, amplitude=0.02))
     target = _f32(I.smooth_field(n, 7, amplitude=0.02))
@@ -160,6 +161,41 @@ def test_rollout_gradient_vs_central_differences():
               - rollout_loss(u0, F - d, None, tau, steps, target)) / 2e-6
         say(f"  g[{a}]: adjoint {dF[a]:.6e}  FD {fd:.6e}")
         assert abs(dF[a] - fd) <= 1e-4 * abs(fd)
+
+
+@pytest.mark.timeout(600)
+def test_rollout_gradient_at_workload_size_vs_central_difference():
+    """The differentiable workload as the bench times it: periodic 128^3,
+    smooth u0 (seed 2024, amplitude 0.02), target seed 7, g = (1e-6, 0, 0),
+    tau = 0.6, 400 steps, checkpoints every 20.  One directional derivative
+    of the GPU gradient (a smooth direction, seed 101) against an FP64
+    central difference of the oracle (eps = 1e-4), and the force gradient's
+    x component against one at eps = 1e-6; bar 1e-4 relative."""
+    n, tau, steps = 128, 0.6, 400
+    say("rollout gradient at 128^3 x 400 steps vs one central difference each")
+    u0 = _f32(I.smooth_field(n, 2024, amplitude=0.02))
+    target = _f32(I.smooth_field(n, 7, amplitude=0.02))
+    F = np.array([1e-6, 0.0, 0.0])
+    du0, dF, _ = _gpu_grad(u0, target, F, None, tau, steps, 20)
+    torch.cuda.empty_cache()
+    v = I.smooth_field(n, 101, amplitude=1.0)
+    eps = 1e-4
+    losses = []
+    for sgn in (1, -1):
+        say(f"  oracle rollout u0 {'+' if sgn > 0 else '-'} eps v ...")
+        losses.append(rollout_loss(u0 + sgn * eps * v, F, None, tau, steps, target))
+    fd = (losses[0] - losses[1]) / (2 * eps)
+    ad = float((du0 * v).sum())
+    say(f"  direction 101: adjoint {ad:.6e}  FD {fd:.6e}  rel {abs(ad - fd) / abs(fd):.2e}")
+    assert abs(ad - fd) <= 1e-4 * abs(fd)
+    d = np.array([1e-6, 0.0, 0.0])
+    losses = []
+    for sgn in (1, -1):
+        say(f"  oracle rollout g {'+' if sgn > 0 else '-'} eps ...")
+        losses.append(rollout_loss(u0, F + sgn * d, None, tau, steps, target))
+    fdg = (losses[0] - losses[1]) / 2e-6
+    say(f"  g[0]: adjoint {dF[0]:.6e}  FD {fdg:.6e}  rel {abs(dF[0] - fdg) / abs(fdg):.2e}")
+    assert abs(dF[0] - fdg) <= 1e-4 * abs(fdg)
 
 
 def test_checkpoint_spacing_gives_identical_gradients():

@@ -86,7 +86,7 @@ def test_graph_replays_across_a_stream_change():
     """Graphs replayed on one stream, the context moved to a second stream,
     replays there, then the graph length changed and the context destroyed:
     the results match plain launches and the graphs of the first stream are
-    released only after their replays (waited on the stream they ran on)."""
+    released only after their replays (waited through the replay event)."""
     say("graph replays across lbm_set_stream")
     ref = _sim().step(8 * 5 + 3)
     g = _sim().use_graphs(8)
@@ -96,7 +96,7 @@ def test_graph_replays_across_a_stream_change():
     A.lbm_set_stream(g.ctx, ctypes.c_void_p(s.cuda_stream))
     g.stream = s
     g.step(8 * 3 + 3)
-    g.use_graphs(4)  # waits for the latest replay, on s
+    g.use_graphs(4)  # waits for the latest replay (queued on s)
     s.synchronize()
     torch.cuda.synchronize()
     assert g.t == ref.t and torch.equal(_bytes(g), _bytes(ref))
@@ -105,6 +105,26 @@ def test_graph_replays_across_a_stream_change():
     s.synchronize()
     assert torch.equal(_bytes(g), _bytes(ref))
     del g
+
+
+def test_graphs_released_after_their_replay_stream_is_destroyed():
+    """Graphs replayed on a stream the caller then destroys: switching the
+    graphs off afterwards waits for those replays through the event recorded
+    after them (not on the dead stream) and succeeds; the results match
+    plain launches."""
+    say("graph replays on a destroyed stream")
+    hip = ctypes.CDLL("libamdhip64.so.7")  # the runtime instance torch has loaded
+    ref = _sim().step(8 * 4)
+    g = _sim().use_graphs(8)
+    torch.cuda.synchronize()
+    s = ctypes.c_void_p()
+    assert hip.hipStreamCreate(ctypes.byref(s)) == 0
+    A.lbm_set_stream(g.ctx, s)
+    g.step(8 * 4)
+    A.lbm_set_stream(g.ctx, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert hip.hipStreamDestroy(s) == 0
+    g.use_graphs(0)
+    assert torch.equal(_bytes(g), _bytes(ref))
 
 
 def test_interleaved_contexts_are_independent():

@@ -250,3 +250,28 @@ def test_sampled_adjoint_step_at_rollout_size():
         worst = max(worst, e)
         assert e <= 1e-5, (z, y, x, e)
     say(f"  worst relative error {worst:.2e}")
+
+
+@pytest.mark.parametrize("storage,s", [("f32", 0), ("f16", 12)])
+def test_sampled_step_unpadded_500(storage, s):
+    """The domain sweep's unpadded layout at one of its sizes (x_align = 1:
+    rows 500 cells apart, so rows start at every 16-byte offset and the
+    64-cell segments straddle row ends): 500^3 porous box (10% spheres,
+    seed 12345), sampled one-step parity, rows near both ends included."""
+    n = 500
+    say(f"unpadded {n}^3 porous, {storage}: sampled one-step parity")
+    flags = I.sphere_pack((n, n, n), 0.10, seed=12345)
+    u0 = I.shear_waves((n, n, n), seed=8, amplitude=0.02)
+    u0[:, flags & 1 == 1] = 0
+    sim = LBM((n, n, n), TAU, F, storage, flags=flags, u0=torch.from_numpy(u0), x_align=1,
+              f16_scale_log2=s)
+    assert sim.x_stride == n
+    del u0
+    rng = np.random.default_rng(500)
+    fluid = (flags & 1) == 0
+    zyx = [(z, y, x) for z, y, x in [(0, 0, 0), (n - 1, n - 1, n - 1), (3, 7, n - 1), (9, 2, 0),
+                                     (n - 1, 0, 447), (1, n - 1, 448), (5, 5, 63), (6, 6, 64)]
+           if fluid[z, y, x]]
+    cells = [(z * n + y) * n + x for z, y, x in zyx]
+    cells += list(rng.choice(np.flatnonzero(fluid.ravel()), size=160, replace=False))
+    _sampled_step(sim, flags, storage, s, cells, TAU, F, None)

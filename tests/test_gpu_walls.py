@@ -41,7 +41,7 @@ def _moving_flags(shape, seed):
 def test_moving_wall_streaming(storage):
     """tau = +inf, F = 0: pull with bounce-back plus the moving-wall term.
     The GPU adds the rounded term in the storage's arithmetic, so the match
-    is to that rounding; the moving-wall cells carry +infinity markers."""
+    is to that rounding; the moving-wall cells carry the moving-wall marker."""
     shape = (5, 6, 70)
     uw = (0.04, -0.03, 0.02)
     say("moving-wall streaming", storage, shape)
