@@ -531,43 +531,24 @@ int oracle_adjoint_seed(int nx, int ny, int nz, const double *F,
   return 0;
 }
 
-/* One reverse step n+1 -> n.  Given f*(n) and lambda^{n+1}:
- *   f(n+1) = stream(f*(n));  mu = J(f(n+1))^T lambda^{n+1} at fluid cells;
- *   dLdF += JF(f(n+1))^T lambda^{n+1} at forced fluid cells;
- *   lambda^n = stream^T(mu): the transpose of the push-with-bounce-back is
- *   the gather  lambda^n_i(y) = mu_i(y + c_i) if that cell is fluid, else
- *   mu_{opp i}(y).  The moving-wall correction is a constant of the
- *   streaming, so it enters f(n+1) but not the transpose. */
-int oracle_adjoint_step(int nx, int ny, int nz, double tau, const double *F,
-                        const uint8_t *flags, const double *wall_u, int incomp,
-                        const double *fn_abi,
-                        const double *lam_np1_abi, double *lam_n_abi,
-                        double *dLdF) {
-  if (lattice_init() || check_dims(nx, ny, nz)) return -1;
-  grid g = {nx, ny, nz, (long)nx * ny * nz};
-  double omega = 1.0 / tau;
-  double *a = malloc((size_t)g.n * Q * sizeof(double));
-  double *b = calloc((size_t)g.n * Q, sizeof(double));
-  double *lam = malloc((size_t)g.n * Q * sizeof(double));
-  double *mu = calloc((size_t)g.n * Q, sizeof(double));
-  double *dF = calloc((size_t)g.n * 3, sizeof(double));
-  if (!a || !b || !lam || !mu || !dF) {
-    free(a);
-    free(b);
-    free(lam);
-    free(mu);
-    free(dF);
-    return -2;
-  }
-  load_abi(&g, fn_abi, a);
-  load_abi(&g, lam_np1_abi, lam);
-  stream_push(&g, flags, wall_u, a, b);
+/* The collision's part of a reverse step (internal layout): at every fluid
+ * cell, mu = J(f)^T lambda, the transposed Jacobian of the collision at the
+ * pre-collision state f (explicit 19x19 matrix of collide_jacobian), and
+ * dLdF += JF(f)^T lambda on forced fluid cells; mu = 0 on solid cells. */
+static int adjoint_collide_aos(const grid *g, double omega, const double *F,
+                               const uint8_t *flags, int incomp, const double *f,
+                               const double *lam, double *mu, double *dLdF) {
+  double *dF = calloc((size_t)g->n * 3, sizeof(double));
+  if (!dF) return -2;
 #pragma omp parallel for schedule(static)
-  for (long c = 0; c < g.n; ++c) {
-    if (is_solid(flags, c)) continue;
+  for (long c = 0; c < g->n; ++c) {
+    if (is_solid(flags, c)) {
+      for (int i = 0; i < Q; ++i) mu[c * Q + i] = 0.0;
+      continue;
+    }
     double Fc[3], J[Q][Q], JF[Q][3];
     cell_force(flags, c, F, Fc);
-    collide_jacobian(omega, Fc, incomp, b + c * Q, J, JF);
+    collide_jacobian(omega, Fc, incomp, f + c * Q, J, JF);
     for (int jj = 0; jj < Q; ++jj) {
       double s = 0.0;
       for (int i = 0; i < Q; ++i) s += lam[c * Q + i] * J[i][jj];
@@ -580,32 +561,113 @@ int oracle_adjoint_step(int nx, int ny, int nz, double tau, const double *F,
         dF[c * 3 + d] = s;
       }
   }
-  /* transpose of stream_push, as a gather */
+  double acc[3] = {0, 0, 0};
+  for (long c = 0; c < g->n; ++c)
+    for (int d = 0; d < 3; ++d) acc[d] += dF[c * 3 + d];
+  for (int d = 0; d < 3; ++d) dLdF[d] += acc[d];
+  free(dF);
+  return 0;
+}
+
+/* The transpose of stream_push (internal layout), as a gather:
+ * lam_i(y) = mu_i(y + c_i) if that cell is fluid, else mu_{opp i}(y); 0 on
+ * solid cells.  The moving-wall correction is a constant of the streaming
+ * and has no transpose. */
+static void stream_transpose_aos(const grid *g, const uint8_t *flags, const double *mu,
+                                 double *lam) {
 #pragma omp parallel for schedule(static)
-  for (int z = 0; z < nz; ++z)
-    for (int y = 0; y < ny; ++y)
-      for (int x = 0; x < nx; ++x) {
-        long c = cell(&g, x, y, z);
+  for (int z = 0; z < g->nz; ++z)
+    for (int y = 0; y < g->ny; ++y)
+      for (int x = 0; x < g->nx; ++x) {
+        long c = cell(g, x, y, z);
         for (int i = 0; i < Q; ++i) {
           double v = 0.0;
           if (!is_solid(flags, c)) {
-            long t = cell(&g, wrap(x + C[i][0], nx), wrap(y + C[i][1], ny),
-                          wrap(z + C[i][2], nz));
+            long t = cell(g, wrap(x + C[i][0], g->nx), wrap(y + C[i][1], g->ny),
+                          wrap(z + C[i][2], g->nz));
             v = !is_solid(flags, t) ? mu[t * Q + i] : mu[c * Q + OPP[i]];
           }
-          a[c * Q + i] = v;
+          lam[c * Q + i] = v;
         }
       }
-  store_abi(&g, a, lam_n_abi);
-  double acc[3] = {0, 0, 0};
-  for (long c = 0; c < g.n; ++c)
-    for (int d = 0; d < 3; ++d) acc[d] += dF[c * 3 + d];
-  for (int d = 0; d < 3; ++d) dLdF[d] += acc[d];
+}
+
+/* One reverse step n+1 -> n.  Given f*(n) and lambda^{n+1}:
+ *   f(n+1) = stream(f*(n));  mu = J(f(n+1))^T lambda^{n+1} at fluid cells;
+ *   dLdF += JF(f(n+1))^T lambda^{n+1} at forced fluid cells;
+ *   lambda^n = stream^T(mu).  The moving-wall correction is a constant of
+ *   the streaming, so it enters f(n+1) but not the transpose. */
+int oracle_adjoint_step(int nx, int ny, int nz, double tau, const double *F,
+                        const uint8_t *flags, const double *wall_u, int incomp,
+                        const double *fn_abi,
+                        const double *lam_np1_abi, double *lam_n_abi,
+                        double *dLdF) {
+  if (lattice_init() || check_dims(nx, ny, nz)) return -1;
+  grid g = {nx, ny, nz, (long)nx * ny * nz};
+  double *a = malloc((size_t)g.n * Q * sizeof(double));
+  double *b = calloc((size_t)g.n * Q, sizeof(double));
+  double *lam = malloc((size_t)g.n * Q * sizeof(double));
+  double *mu = calloc((size_t)g.n * Q, sizeof(double));
+  int rc = (a && b && lam && mu) ? 0 : -2;
+  if (!rc) {
+    load_abi(&g, fn_abi, a);
+    load_abi(&g, lam_np1_abi, lam);
+    stream_push(&g, flags, wall_u, a, b);
+    rc = adjoint_collide_aos(&g, 1.0 / tau, F, flags, incomp, b, lam, mu, dLdF);
+  }
+  if (!rc) {
+    stream_transpose_aos(&g, flags, mu, a);
+    store_abi(&g, a, lam_n_abi);
+  }
   free(a);
   free(b);
   free(lam);
   free(mu);
-  free(dF);
+  return rc;
+}
+
+/* The collision's part of the reverse step on its own (interface layout):
+ * mu = J(f_pre)^T lambda and dLdF += JF(f_pre)^T lambda at a given
+ * pre-collision state f_pre. */
+int oracle_adjoint_collide(int nx, int ny, int nz, double tau, const double *F,
+                           const uint8_t *flags, int incomp, const double *fpre_abi,
+                           const double *lam_abi, double *mu_abi, double *dLdF) {
+  if (lattice_init() || check_dims(nx, ny, nz)) return -1;
+  grid g = {nx, ny, nz, (long)nx * ny * nz};
+  double *f = malloc((size_t)g.n * Q * sizeof(double));
+  double *lam = malloc((size_t)g.n * Q * sizeof(double));
+  double *mu = malloc((size_t)g.n * Q * sizeof(double));
+  int rc = (f && lam && mu) ? 0 : -2;
+  if (!rc) {
+    load_abi(&g, fpre_abi, f);
+    load_abi(&g, lam_abi, lam);
+    rc = adjoint_collide_aos(&g, 1.0 / tau, F, flags, incomp, f, lam, mu, dLdF);
+  }
+  if (!rc) store_abi(&g, mu, mu_abi);
+  free(f);
+  free(lam);
+  free(mu);
+  return rc;
+}
+
+/* The streaming's part on its own (interface layout): lambda = stream^T(mu),
+ * the transposed streaming with half-way bounce-back. */
+int oracle_stream_transpose(int nx, int ny, int nz, const uint8_t *flags,
+                            const double *mu_abi, double *lam_abi) {
+  if (lattice_init() || check_dims(nx, ny, nz)) return -1;
+  grid g = {nx, ny, nz, (long)nx * ny * nz};
+  double *mu = malloc((size_t)g.n * Q * sizeof(double));
+  double *lam = malloc((size_t)g.n * Q * sizeof(double));
+  if (!mu || !lam) {
+    free(mu);
+    free(lam);
+    return -2;
+  }
+  load_abi(&g, mu_abi, mu);
+  stream_transpose_aos(&g, flags, mu, lam);
+  store_abi(&g, lam, lam_abi);
+  free(mu);
+  free(lam);
   return 0;
 }
 

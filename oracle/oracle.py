@@ -46,6 +46,8 @@ def load(path):
         "oracle_adjoint_seed": [i, i, i, dp, u8p, i, dp, dp, dp, dp, dp],
         "oracle_adjoint_step": [i, i, i, d, dp, u8p, dp, i, dp, dp, dp, dp],
         "oracle_adjoint_init": [i, i, i, u8p, i, dp, dp, dp, dp, dp],
+        "oracle_adjoint_collide": [i, i, i, d, dp, u8p, i, dp, dp, dp, dp],
+        "oracle_stream_transpose": [i, i, i, u8p, dp, dp],
         "oracle_host_copy": [dp, dp, l, i],
         "oracle_threads": [],
         "oracle_set_threads": [i],
@@ -225,6 +227,31 @@ def adjoint_step(fn, lam_np1, tau, F=(0.0, 0.0, 0.0), flags=None, wall_u=None,
                                      _wall(wall_u), int(incompressible), _d(fn), _d(lam_np1),
                                      _d(lam), _d(dF)), "adjoint_step")
     return lam, dF
+
+
+def adjoint_collide(f_pre, lam, tau, F=(0.0, 0.0, 0.0), flags=None, incompressible=False):
+    """(mu = J(f_pre)^T lam, dL/dF contribution JF(f_pre)^T lam): the collision's
+    part of a reverse step at a pre-collision state f_pre."""
+    f_pre = np.ascontiguousarray(f_pre, dtype=np.float64)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    _, nz, ny, nx = f_pre.shape
+    fl = _flags(flags, (nz, ny, nx))
+    mu = np.zeros_like(f_pre)
+    dF = np.zeros(3)
+    _check(lib().oracle_adjoint_collide(nx, ny, nz, float(tau), _d(_vec3(F)), _u8(fl),
+                                        int(incompressible), _d(f_pre), _d(lam), _d(mu), _d(dF)),
+           "adjoint_collide")
+    return mu, dF
+
+
+def stream_transpose(mu, flags=None):
+    """lam = stream^T(mu): the transposed streaming with bounce-back (a gather)."""
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    _, nz, ny, nx = mu.shape
+    fl = _flags(flags, (nz, ny, nx))
+    lam = np.zeros_like(mu)
+    _check(lib().oracle_stream_transpose(nx, ny, nz, _u8(fl), _d(mu), _d(lam)), "stream_transpose")
+    return lam
 
 
 def adjoint_init(lam0, u0, flags=None, rho0=None, incompressible=False):

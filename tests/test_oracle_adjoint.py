@@ -56,6 +56,61 @@ def test_transposed_streaming_dot_product_exact():
     assert not PTy[:, flags == 1].any()
 
 
+def test_stream_transpose_dot_product_exact():
+    """The exported transposed streaming: <P x, y> == <x, P^T y> exactly for
+    the streaming P of the forward oracle (integer data), and the adjoint
+    step is P^T after the collision part at the streamed state, bit for bit."""
+    shape = (4, 5, 7)
+    flags = I.random_flags(shape, 9, solid_fraction=0.3)
+    rng = np.random.default_rng(10)
+    x = rng.integers(-50, 50, size=(19,) + shape).astype(np.float64)
+    y = rng.integers(-50, 50, size=(19,) + shape).astype(np.float64)
+    x[:, flags == 1] = 0
+    y[:, flags == 1] = 0
+    PTy = O.stream_transpose(y, flags)
+    assert (O.stream(x, flags, n=1) * y).sum() == (x * PTy).sum()
+    assert not PTy[:, flags == 1].any()
+    tau, F = 0.7, (1e-3, -2e-3, 5e-4)
+    fn = O.step(O.init(shape, flags, None, 0.03 * (rng.random((3,) + shape) - 0.5)), tau, F, flags)
+    lam = rng.standard_normal((19,) + shape)
+    lam[:, flags == 1] = 0
+    mu, dF1 = O.adjoint_collide(O.stream(fn, flags), lam, tau, F, flags)
+    lam_n, dF2 = O.adjoint_step(fn, lam, tau, F, flags)
+    assert np.array_equal(O.stream_transpose(mu, flags), lam_n) and np.array_equal(dF1, dF2)
+
+
+def test_adjoint_collide_vs_central_differences():
+    """sum lam . (Omega(f + e v) - Omega(f - e v)) / 2e == sum v . mu on a
+    grid of cells (Omega applied cell by cell through oracle.collide), and
+    the same for a force perturbation against dL/dF."""
+    shape = (2, 3, 4)
+    _, w, _ = R.e_w_opp()
+    rng = np.random.default_rng(21)
+    flags = np.zeros(shape, np.uint8)
+    flags[0, 1, 2] = 2  # one no-force cell
+    f = w[:, None, None, None] * (1 + 0.1 * rng.standard_normal((19,) + shape))
+    lam = rng.standard_normal((19,) + shape)
+    v = rng.standard_normal((19,) + shape)
+    tau, F = 0.66, np.array([1e-2, -2e-2, 5e-3])
+    mu, dF = O.adjoint_collide(f, lam, tau, F, flags)
+
+    def omega(ff, FF):
+        out = np.zeros_like(ff)
+        for z, y_, x in np.ndindex(shape):
+            Fc = FF if flags[z, y_, x] != 2 else np.zeros(3)
+            out[:, z, y_, x] = O.collide(tau, Fc, ff[:, z, y_, x])
+        return out
+
+    h = 1e-6
+    fd = ((omega(f + h * v, F) - omega(f - h * v, F)) * lam).sum() / (2 * h)
+    assert abs(fd - (v * mu).sum()) <= 1e-8 * abs(fd)
+    for a in range(3):
+        d = np.zeros(3)
+        d[a] = h
+        fdF = ((omega(f, F + d) - omega(f, F - d)) * lam).sum() / (2 * h)
+        assert abs(fdF - dF[a]) <= 1e-8 * abs(fdF)
+
+
 def rollout_loss(u0, F, flags, tau, steps, target, wall_u=None, inc=False):
     """L = mean over fluid cells and components of (u_T - u*)^2."""
     shape = u0.shape[1:]

@@ -93,6 +93,14 @@ def _walls_full_adj():
     TA.test_full_adjoint_vs_central_differences(True, True, False)
 
 
+def _adj_collide_fd():
+    TA.test_adjoint_collide_vs_central_differences()
+
+
+def _transpose_dot():
+    TA.test_stream_transpose_dot_product_exact()
+
+
 def _noforce_gain():
     TSW.test_noforce_switch_momentum_gain(1)
 
@@ -150,9 +158,13 @@ MUTATIONS = {
     "moving_bit_ignored": ("else if (wall_u && is_moving(flags, t))",
                            "else if (wall_u && 0 && is_moving(flags, t))",
                            [_momentum, _couette]),
-    "adjoint_recompute_without_walls": ("stream_push(&g, flags, wall_u, a, b);\n#pragma omp parallel for schedule(static)\n  for (long c = 0; c < g.n; ++c) {\n    if (is_solid(flags, c)) continue;\n    double Fc[3], J",
-                                        "stream_push(&g, flags, NULL, a, b);\n#pragma omp parallel for schedule(static)\n  for (long c = 0; c < g.n; ++c) {\n    if (is_solid(flags, c)) continue;\n    double Fc[3], J",
+    "adjoint_recompute_without_walls": ("stream_push(&g, flags, wall_u, a, b);\n    rc = adjoint_collide_aos",
+                                        "stream_push(&g, flags, NULL, a, b);\n    rc = adjoint_collide_aos",
                                         [_walls_full_adj]),
+    "adjoint_collide_transposed": ("s += lam[c * Q + i] * J[i][jj];", "s += lam[c * Q + i] * J[jj][i];",
+                                   [_adj_collide_fd, _full_adj]),
+    "stream_transpose_without_bounce": ("v = !is_solid(flags, t) ? mu[t * Q + i] : mu[c * Q + OPP[i]];",
+                                        "v = mu[t * Q + i];", [_dot, _transpose_dot]),
     "incompressible_equilibrium_rho": ("incomp ? W[i] * (rho + poly)", "incomp ? W[i] * rho * (1.0 + poly)",
                                        [_inc_eq]),
     "incompressible_velocity": ("(j[d] + 0.5 * F[d]) / (incomp ? 1.0 : rho)", "(j[d] + 0.5 * F[d]) / rho",
