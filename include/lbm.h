@@ -228,6 +228,19 @@ lbm_status lbm_macroscopics_f64(lbm_ctx* ctx, double* rho, double* u);
  * Errors: LBM_E_ARG, LBM_E_HIP. */
 lbm_status lbm_reduce(lbm_ctx* ctx, double* out5);
 
+/* lbm_reduce without the context's scratch, for callers that cannot
+ * allocate device memory or hand over a workspace (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and result, bit for bit, with the partial sums in a static device
+ * array of the library -- 1024 records of 5 doubles (40 KiB) per GPU, held
+ * from the first lbm_init on that GPU until the process ends.  The
+ * reduction uses exactly that many records for any grid size, so no grid is
+ * too large.  It allocates nothing and does not synchronise.  Every call on
+ * one GPU shares that GPU's array: calls that overlap in time on one GPU
+ * (other streams, other threads, other contexts) race and must be ordered
+ * by the caller.  Errors: LBM_E_ARG, LBM_E_HIP. */
+lbm_status lbm_reduce_noalloc(lbm_ctx* ctx, double* out5);
+
 /* Context state: which grid (0 = grid_a, 1 = grid_b) holds f*(t), the step
  * count t, and the stream.  lbm_set_current declares that grid `parity`
  * holds f*(t) (for restoring a saved state). */

@@ -47,6 +47,7 @@ _SIGNATURES = {
     "lbm_macroscopics": (_st, [_vp, _vp, _vp]),
     "lbm_macroscopics_f64": (_st, [_vp, _vp, _vp]),
     "lbm_reduce": (_st, [_vp, _vp]),
+    "lbm_reduce_noalloc": (_st, [_vp, _vp]),
     "lbm_current": (C.c_int32, [_vp]),
     "lbm_time": (C.c_int64, [_vp]),
     "lbm_set_current": (_st, [_vp, C.c_int32, C.c_int64]),
@@ -164,6 +165,10 @@ def lbm_macroscopics_f64(ctx, rho, u):
 
 def lbm_reduce(ctx, out5):
     check(lib().lbm_reduce(ctx, out5))
+
+
+def lbm_reduce_noalloc(ctx, out5):
+    check(lib().lbm_reduce_noalloc(ctx, out5))
 
 
 def lbm_current(ctx):

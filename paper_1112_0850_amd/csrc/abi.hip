@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/lbm.h"
@@ -118,6 +119,44 @@ lbm_status check_params(const lbm_params* p, Sizes* sz) {
 
 }  // namespace
 
+// Partial sums of lbm_reduce_noalloc: one record of 5 doubles per reduction
+// block, in a file-scope device array (each GPU the library runs on holds
+// its own copy until the process ends).  Host code never hands the array's
+// name to a kernel -- in host code that name is a stand-in, not a device
+// address -- but the address hipGetSymbolAddress returns on each device,
+// taken once per device by lbm_init with that device current.
+constexpr size_t kNoallocScratchDoubles = size_t(lbm::kReduceBlocks) * 5;
+static __device__ __align__(256) double noalloc_scratch[kNoallocScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[kMaxDevices] = {};
+
+// Device address of noalloc_scratch on the current device (looked up once
+// per device).
+lbm_status noalloc_scratch_here(int* dev_out, double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "current device");
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(LBM_E_UNSUPPORTED, "device %d is beyond the %d devices the library tracks", dev,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess) return hip_fail(e, "address of the static reduction scratch");
+    g_noalloc_ptr[dev] = static_cast<double*>(p);
+  }
+  *dev_out = dev;
+  *out = g_noalloc_ptr[dev];
+  return LBM_OK;
+}
+
+}  // namespace
+
 struct lbm_ctx {
   lbm_params p;
   Sizes sz;
@@ -135,6 +174,8 @@ struct lbm_ctx {
   hipStream_t capture_stream;  // library-owned, used only to capture the graphs
   hipEvent_t replay_done;      // recorded after the latest graph replay
   bool replayed;               // replay_done has been recorded
+  int device;                  // current device at lbm_init
+  double* noalloc;             // that device's address of noalloc_scratch
 };
 
 namespace {
@@ -272,8 +313,14 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* grid_a, void* grid
   if ((rho0 && (reinterpret_cast<uintptr_t>(rho0) & 3u)) ||
       (u0 && (reinterpret_cast<uintptr_t>(u0) & 3u)))
     return fail(LBM_E_ARG, "rho0 and u0 must be 4-byte aligned");
+  int dev = 0;
+  double* noalloc = nullptr;
+  st = noalloc_scratch_here(&dev, &noalloc);
+  if (st != LBM_OK) return st;
   lbm_ctx* c = new (std::nothrow) lbm_ctx;
   if (!c) return fail(LBM_E_ARG, "out of host memory");
+  c->device = dev;
+  c->noalloc = noalloc;
   c->p = *p;
   c->sz = sz;
   c->geo = lbm::make_geo(p->nx, p->ny, p->nz, int(sz.xs), sz.dir);
@@ -366,6 +413,23 @@ lbm_status lbm_reduce(lbm_ctx* c, double* out5) {
   if (!out5) return fail(LBM_E_ARG, "out5 is NULL");
   hipError_t e = lbm::launch_reduce(c->p.storage, c->geo, c->ph, c->grid[c->cur], c->flags,
                                     c->scratch, out5, c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "reduction launch");
+}
+
+lbm_status lbm_reduce_noalloc(lbm_ctx* c, double* out5) {
+  static_assert(kNoallocScratchDoubles >= size_t(lbm::kReduceBlocks) * 5,
+                "the static scratch must hold every partial record of the reduction");
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!out5) return fail(LBM_E_ARG, "out5 is NULL");
+  // The reduction writes exactly kReduceBlocks partial records for any grid
+  // size (its blocks stride over the cells), which is the array's capacity;
+  // a launcher that asked for more would be rejected here.
+  if (size_t(lbm::kReduceBlocks) * 5 > kNoallocScratchDoubles)
+    return fail(LBM_E_UNSUPPORTED, "reduction needs more than the %zu static partial sums",
+                kNoallocScratchDoubles);
+  hipError_t e = lbm::launch_reduce(c->p.storage, c->geo, c->ph, c->grid[c->cur], c->flags,
+                                    c->noalloc, out5, c->stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "reduction launch");
 }
 
