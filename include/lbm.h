@@ -265,36 +265,44 @@ lbm_status lbm_restore(lbm_ctx* ctx, const void* src, int64_t t);
  * macroscopic fields (FP32 adjoint arithmetic), with either equilibrium and
  * with moving walls (the wall velocity is a constant of the map, so it
  * enters the recomputed state but not the transpose; no gradient is formed
- * for it).  lambda^n = dL/d f*(n) is FP32 in the grid layout (grid_bytes
- * of floats, direction arrays dir_stride apart); its solid-cell and padding
- * slots must be zero when first used (the seed writes zeros there and the step never
- * writes them).  dL/dF is accumulated per thread block in an FP64 partials
- * buffer (adj_partials_bytes) without atomics; lbm_adjoint_finish_dF reduces
- * it in a fixed order.  Errors: LBM_E_UNSUPPORTED for other storage types,
- * LBM_E_ARG, LBM_E_HIP. */
+ * for it).  The carried adjoint state is nu^n = dL/df(n), the adjoint of
+ * the PRE-collision populations f(n) = P f*(n-1) (P: the pull streaming with
+ * half-way bounce-back); with lambda^n = dL/df*(n) = P^T nu^{n+1},
+ *   nu^n = J(f(n))^T lambda^n,   dL/dF += JF(f(n))^T lambda^n,
+ * J and JF the collision's Jacobians with respect to f and the force.  Each
+ * call gathers what it needs (P^T as a pull along +c_i, P along -c_i) and
+ * stores nu at the cell itself, so every store is aligned.  nu grids are
+ * FP32 in the grid layout (grid_bytes of floats, direction arrays
+ * dir_stride apart); the kernels write every cell of them, the resting solid
+ * marker on solid cells, and never the padding.  dL/dF is accumulated per
+ * thread block in an FP64 partials buffer (adj_partials_bytes) without
+ * atomics; lbm_adjoint_finish_dF reduces it in a fixed order.  A rollout of
+ * T steps: seed with f*(T-1); step with f*(n-1) for n = T-1 .. 1; init.
+ * Errors: LBM_E_UNSUPPORTED for other storage types, LBM_E_ARG, LBM_E_HIP. */
 
-/* Seed from dL/drho_T (float [nz][ny][nx] or NULL = 0) and dL/du_T (float
- * [3][nz][ny][nx] or NULL = 0) at the current time level:
+/* Seed: nu^T = J(f(T))^T lambda^T, f(T) = P f*(T-1) gathered from fstar_prev
+ * (= f*(T-1), grid layout), with lambda^T from dL/drho_T (float [nz][ny][nx]
+ * or NULL = 0) and dL/du_T (float [3][nz][ny][nx] or NULL = 0):
  *   lambda^T_i = dL/drho + dL/du . (c_i - u)/rho
- * (dL/drho + dL/du . c_i for the incompressible equilibrium);
- * (re)initialises the partials with the term -dL/du / (2 rho) (rho -> 1 for
- * the incompressible equilibrium). */
-lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const float* dL_drho, const float* dL_du,
-                            float* lam_T, double* dLdF_partials);
+ * (dL/drho + dL/du . c_i for the incompressible equilibrium), where rho and
+ * u are the moments of f(T) -- equal to the fields lbm_macroscopics reads
+ * from f*(T).  (Re)initialises the partials with -dL/du / (2 rho) + JF^T
+ * lambda^T (rho -> 1 for the incompressible equilibrium). */
+lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const void* fstar_prev, const float* dL_drho,
+                            const float* dL_du, float* nu_T, double* dLdF_partials);
 
-/* One reverse step n+1 -> n:  recompute f(n+1) = stream(fstar_n), apply the
- * transposed collision Jacobian mu = (dOmega/df)^T lambda^{n+1}, add
- * (dOmega/dF)^T lambda^{n+1} to the partials, and push-store the transposed
- * streaming:  lambda^n_i(x - c_i) = mu_i(x) if x - c_i is fluid, else
- * lambda^n_{opp i}(x) = mu_i(x).  fstar_n is the forward state f*(n) in the
- * grid layout; lam_np1 and lam_n must differ. */
-lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* fstar_n, const float* lam_np1,
-                            float* lam_n, double* dLdF_partials);
+/* One reverse step n+1 -> n: lambda^n_i(x) = nu^{n+1}_i(x + c_i), or
+ * nu^{n+1}_{opp i}(x) if x + c_i is solid; f(n) = P fstar_prev with
+ * fstar_prev = f*(n-1); nu_n <- J(f(n))^T lambda^n; partials += JF^T
+ * lambda^n.  nu_n must differ from both inputs. */
+lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* fstar_prev, const float* nu_np1,
+                            float* nu_n, double* dLdF_partials);
 
-/* Initial-state adjoint: dL/du0 = sum_i lambda^0_i d f^eq_i/du (rho0, u0),
- * written as float [3][nz][ny][nx] (0 on solid cells).  rho0 / u0 as passed
- * to lbm_init (u0 NULL = rest, rho0 NULL = 1). */
-lbm_status lbm_adjoint_init(lbm_ctx* ctx, const float* lam_0, const float* rho0,
+/* Initial-state adjoint from nu^1: lambda^0 = P^T nu^1 (gathered as above),
+ * dL/du0 = sum_i lambda^0_i d f^eq_i/du (rho0, u0), written as float
+ * [3][nz][ny][nx] (0 on solid cells).  rho0 / u0 as passed to lbm_init
+ * (u0 NULL = rest, rho0 NULL = 1). */
+lbm_status lbm_adjoint_init(lbm_ctx* ctx, const float* nu_1, const float* rho0,
                             const float* u0, float* dL_du0);
 
 /* Fixed-order reduction of the partials into dLdF3 (3 doubles, device). */

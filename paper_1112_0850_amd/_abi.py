@@ -55,7 +55,7 @@ _SIGNATURES = {
     "lbm_refresh_solids": (_st, [_vp]),
     "lbm_save": (_st, [_vp, _vp]),
     "lbm_restore": (_st, [_vp, _vp, C.c_int64]),
-    "lbm_adjoint_seed": (_st, [_vp, _vp, _vp, _vp, _vp]),
+    "lbm_adjoint_seed": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "lbm_adjoint_step": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_adjoint_init": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "lbm_adjoint_finish_dF": (_st, [_vp, _vp, _vp]),
@@ -199,16 +199,16 @@ def lbm_restore(ctx, src, t):
     check(lib().lbm_restore(ctx, src, int(t)))
 
 
-def lbm_adjoint_seed(ctx, dL_drho, dL_du, lam_T, partials):
-    check(lib().lbm_adjoint_seed(ctx, dL_drho, dL_du, lam_T, partials))
+def lbm_adjoint_seed(ctx, fstar_prev, dL_drho, dL_du, nu_T, partials):
+    check(lib().lbm_adjoint_seed(ctx, fstar_prev, dL_drho, dL_du, nu_T, partials))
 
 
-def lbm_adjoint_step(ctx, fstar_n, lam_np1, lam_n, partials):
-    check(lib().lbm_adjoint_step(ctx, fstar_n, lam_np1, lam_n, partials))
+def lbm_adjoint_step(ctx, fstar_prev, nu_np1, nu_n, partials):
+    check(lib().lbm_adjoint_step(ctx, fstar_prev, nu_np1, nu_n, partials))
 
 
-def lbm_adjoint_init(ctx, lam_0, rho0, u0, dL_du0):
-    check(lib().lbm_adjoint_init(ctx, lam_0, rho0, u0, dL_du0))
+def lbm_adjoint_init(ctx, nu_1, rho0, u0, dL_du0):
+    check(lib().lbm_adjoint_init(ctx, nu_1, rho0, u0, dL_du0))
 
 
 def lbm_adjoint_finish_dF(ctx, partials, dLdF3):

@@ -491,38 +491,44 @@ static lbm_status adj_check(lbm_ctx* c) {
   return LBM_OK;
 }
 
-lbm_status lbm_adjoint_seed(lbm_ctx* c, const float* dL_drho, const float* dL_du, float* lam_T,
-                            double* partials) {
+lbm_status lbm_adjoint_seed(lbm_ctx* c, const void* fstar_prev, const float* dL_drho,
+                            const float* dL_du, float* nu_T, double* partials) {
   lbm_status st = adj_check(c);
   if (st != LBM_OK) return st;
-  if (!lam_T || !partials) return fail(LBM_E_ARG, "lam_T and partials must not be NULL");
-  if (!aligned256(lam_T)) return fail(LBM_E_ARG, "lam_T must be 256-byte aligned");
-  hipError_t e = lbm::launch_adj_seed(c->geo, c->ph, static_cast<const float*>(c->grid[c->cur]),
-                                      c->flags, dL_drho, dL_du, lam_T, partials, c->stream);
+  if (!fstar_prev || !nu_T || !partials)
+    return fail(LBM_E_ARG, "fstar_prev, nu_T and partials must not be NULL");
+  if (fstar_prev == nu_T) return fail(LBM_E_ARG, "fstar_prev and nu_T must differ");
+  if (!aligned256(fstar_prev) || !aligned256(nu_T))
+    return fail(LBM_E_ARG, "fstar_prev and nu_T must be 256-byte aligned");
+  hipError_t e = lbm::launch_adj_seed(c->flags != nullptr, c->geo, c->ph,
+                                      static_cast<const float*>(fstar_prev), c->flags, dL_drho,
+                                      dL_du, nu_T, partials, c->stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint seed launch");
 }
 
-lbm_status lbm_adjoint_step(lbm_ctx* c, const void* fstar_n, const float* lam_np1, float* lam_n,
+lbm_status lbm_adjoint_step(lbm_ctx* c, const void* fstar_prev, const float* nu_np1, float* nu_n,
                             double* partials) {
   lbm_status st = adj_check(c);
   if (st != LBM_OK) return st;
-  if (!fstar_n || !lam_np1 || !lam_n || !partials)
+  if (!fstar_prev || !nu_np1 || !nu_n || !partials)
     return fail(LBM_E_ARG, "adjoint step pointers must not be NULL");
-  if (lam_np1 == lam_n) return fail(LBM_E_ARG, "lam_np1 and lam_n must differ");
-  if (!aligned256(fstar_n) || !aligned256(lam_np1) || !aligned256(lam_n))
+  if (nu_np1 == nu_n || fstar_prev == nu_n) return fail(LBM_E_ARG, "nu_n must differ from the inputs");
+  if (!aligned256(fstar_prev) || !aligned256(nu_np1) || !aligned256(nu_n))
     return fail(LBM_E_ARG, "adjoint grids must be 256-byte aligned");
   hipError_t e = lbm::launch_adj_step(c->flags != nullptr, c->geo, c->ph,
-                                      static_cast<const float*>(fstar_n), c->flags, lam_np1, lam_n,
+                                      static_cast<const float*>(fstar_prev), c->flags, nu_np1, nu_n,
                                       partials, c->stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint step launch");
 }
 
-lbm_status lbm_adjoint_init(lbm_ctx* c, const float* lam_0, const float* rho0, const float* u0,
+lbm_status lbm_adjoint_init(lbm_ctx* c, const float* nu_1, const float* rho0, const float* u0,
                             float* dL_du0) {
   lbm_status st = adj_check(c);
   if (st != LBM_OK) return st;
-  if (!lam_0 || !dL_du0) return fail(LBM_E_ARG, "lam_0 and dL_du0 must not be NULL");
-  hipError_t e = lbm::launch_adj_init(c->geo, c->ph, c->flags, lam_0, rho0, u0, dL_du0, c->stream);
+  if (!nu_1 || !dL_du0) return fail(LBM_E_ARG, "nu_1 and dL_du0 must not be NULL");
+  if (!aligned256(nu_1)) return fail(LBM_E_ARG, "nu_1 must be 256-byte aligned");
+  hipError_t e = lbm::launch_adj_init(c->flags != nullptr, c->geo, c->ph, c->flags, nu_1, rho0, u0,
+                                      dL_du0, c->stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "adjoint init launch");
 }
 

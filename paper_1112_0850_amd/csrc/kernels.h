@@ -51,14 +51,18 @@ hipError_t launch_macro(int storage, bool out_f64, const Geo& g, const PhysParam
                         const void* grid, const uint8_t* flags, void* rho, void* u, hipStream_t s);
 hipError_t launch_reduce(int storage, const Geo& g, const PhysParams& ph, const void* grid,
                          const uint8_t* flags, double* scratch, double* out5, hipStream_t s);
-hipError_t launch_adj_seed(const Geo& g, const PhysParams& ph, const float* fT, const uint8_t* flags,
-                           const float* dL_drho, const float* dL_du, float* lam, double* partials,
-                           hipStream_t s);
-hipError_t launch_adj_step(bool solids, const Geo& g, const PhysParams& ph, const float* fn,
-                           const uint8_t* flags, const float* lam_np1, float* lam_n,
+// Discrete adjoint in pull form (nu = dL/df, the pre-collision adjoint):
+// seed nu^T from dL/drho_T, dL/du_T and f*(T-1); step nu^{n+1} -> nu^n with
+// f*(n-1); init dL/du0 from nu^1.
+hipError_t launch_adj_seed(bool solids, const Geo& g, const PhysParams& ph, const float* fprev,
+                           const uint8_t* flags, const float* dL_drho, const float* dL_du,
+                           float* nu_T, double* partials, hipStream_t s);
+hipError_t launch_adj_step(bool solids, const Geo& g, const PhysParams& ph, const float* fprev,
+                           const uint8_t* flags, const float* nu_np1, float* nu_n,
                            double* partials, hipStream_t s);
-hipError_t launch_adj_init(const Geo& g, const PhysParams& ph, const uint8_t* flags, const float* lam0,
-                           const float* rho0, const float* u0, float* dL_du0, hipStream_t s);
+hipError_t launch_adj_init(bool solids, const Geo& g, const PhysParams& ph, const uint8_t* flags,
+                           const float* nu1, const float* rho0, const float* u0, float* dL_du0,
+                           hipStream_t s);
 hipError_t launch_adj_finish(const Geo& g, const double* partials, double* out3, hipStream_t s);
 hipError_t launch_copy(void* c, const void* a, size_t n16, hipStream_t s);
 // Copy variants for the bandwidth sweep: vec in {1, 2, 4} 16-byte elements per

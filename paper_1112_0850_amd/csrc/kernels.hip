@@ -821,160 +821,195 @@ __device__ __forceinline__ LamMoments lam_moments(const float* lam) {
   return m;
 }
 
-__global__ __launch_bounds__(kBlock) void k_adj_seed(const float* __restrict__ fT,
-                                                     const uint8_t* __restrict__ flags,
-                                                     const float* __restrict__ gr,
-                                                     const float* __restrict__ gu,
-                                                     float* __restrict__ lam,
-                                                     double* __restrict__ partials, Geo g,
-                                                     float Fx, float Fy, float Fz, int incomp) {
+// The adjoint carries nu^n = dL/df(n), the adjoint of the pre-collision state
+// f(n) = P f*(n-1) (P: the pull with half-way bounce-back).  With
+// lambda^n = dL/df*(n) = P^T nu^{n+1}, one reverse step in pull form is
+//   lambda^n_i(x) = nu^{n+1}_i(x + c_i), or nu^{n+1}_{opp i}(x) if x + c_i is
+//                   solid (P^T as a gather along +c_i),
+//   f(n) = P f*(n-1) (the forward pull, gathered along -c_i),
+//   nu^n = J(f(n))^T lambda^n,  dL/dF += JF(f(n))^T lambda^n,
+// and nu^n is stored at x: 19 gathers of nu, 19 of f* and 19 aligned stores
+// per cell (228 B in FP32).  The seed forms lambda^T locally from dL/drho_T
+// and dL/du_T (the moments of f(T) equal those read from f*(T)) and applies
+// the same transposed collision; the initial step gathers lambda^0 = P^T nu^1.
+// The solid cells of a nu grid hold the resting marker, written by the
+// solid lanes, so both gathers test markers as the forward pull does.
+template <bool SOLIDS, bool MOVING, bool SEED>
+__global__ __launch_bounds__(kBlock) void k_adj(const float* __restrict__ fprev,
+                                                const float* __restrict__ nu1,
+                                                float* __restrict__ nu0,
+                                                const uint8_t* __restrict__ flags,
+                                                const float* __restrict__ gr,
+                                                const float* __restrict__ gu,
+                                                double* __restrict__ partials, Geo g,
+                                                Phys<float> ph) {
+  using U = Storage<ST_F32>::U;
   __shared__ double sh[3 * kBlock];
   double d[3] = {0.0, 0.0, 0.0};
-  const Loc l = locate(g);
-  if (l.valid) {
-    const uint32_t c = uint32_t((l.z * g.ny + l.y) * g.nx + l.x);
-    const size_t ncell = size_t(g.nx) * g.ny * g.nz;
-    const uint32_t own = uint32_t(l.z * g.ny + l.y) * uint32_t(g.xs) + uint32_t(l.x);
-    const uint8_t fl = flags ? flags[c] : uint8_t(0);
-    if (fl & FLAG_SOLID) {
-#pragma unroll
-      for (int i = 0; i < Q; ++i) lam[size_t(i) * g.plane + own] = 0.0f;
-    } else {
-      float f[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) f[i] = fT[size_t(i) * g.plane + own];
-      float drho, jx, jy, jz;
-      moments(f, drho, jx, jy, jz);
-      const bool forced = !(fl & FLAG_NOFORCE);
-      const float h = forced ? 0.5f : 0.0f;
-      const float rho_u = incomp ? 1.0f : 1.0f + drho;  // the density dividing j in u
-      const float ux = (jx - h * Fx) / rho_u, uy = (jy - h * Fy) / rho_u,
-                  uz = (jz - h * Fz) / rho_u;
-      const float G = gr ? gr[c] : 0.0f;
-      float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-      if (gu) {
-        gx = gu[c];
-        gy = gu[ncell + c];
-        gz = gu[2 * ncell + c];
-      }
-      const float hx = gx / rho_u, hy = gy / rho_u, hz = gz / rho_u;
-      const float base = incomp ? G : G - (hx * ux + hy * uy + hz * uz);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) lam[size_t(i) * g.plane + own] = base + cdot<float>(i, hx, hy, hz);
-      if (forced) {
-        d[0] = -double(gx) / (2.0 * double(rho_u));
-        d[1] = -double(gy) / (2.0 * double(rho_u));
-        d[2] = -double(gz) / (2.0 * double(rho_u));
-      }
-    }
+  // the step kernel's cell order: 64-cell segments, y-banded rows, XCD remap
+  const int b = blockIdx.x;
+  const int lb = (b < g.nb8) ? ((b & 7) * (g.nb8 >> 3) + (b >> 3)) : b;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int seg = lb * 4 + wave;
+  const int row = seg / g.nseg;
+  Loc l;
+  l.x = (seg - row * g.nseg) * 64 + int(threadIdx.x & 63);
+  {
+    const int rr = row < g.nrows ? row : 0;
+    const int per_band = g.nz * g.yb;
+    const int band = rr / per_band;
+    const int y0 = band * g.yb;
+    const int h = min(g.yb, g.ny - y0);
+    const int idx = rr - band * per_band;
+    l.z = idx / h;
+    l.y = y0 + (idx - l.z * h);
   }
-  block_sum<3>(d, sh);
-  if (threadIdx.x == 0)
-    for (int k = 0; k < 3; ++k) partials[size_t(l.lblock) * 3 + k] = d[k];
-}
-
-template <bool SOLIDS>
-__global__ __launch_bounds__(kBlock) void k_adj_step(const float* __restrict__ fn,
-                                                     const uint8_t* __restrict__ flags,
-                                                     const float* __restrict__ lam1,
-                                                     float* __restrict__ lam0,
-                                                     double* __restrict__ partials, Geo g,
-                                                     Phys<float> ph) {
-  __shared__ double sh[3 * kBlock];
-  double d[3] = {0.0, 0.0, 0.0};
-  const Loc l = locate(g);
+  l.valid = row < g.nrows && l.x < g.nx;
   if (l.valid) {
     const Nbhd n = neighbourhood(g, l);
     const uint8_t fl = SOLIDS ? flags[n.fown] : uint8_t(0);
-    if (!(fl & FLAG_SOLID)) {
-      bool bb[Q], mv[Q];
+    const bool solid = SOLIDS && (fl & FLAG_SOLID);
+    const size_t pb = size_t(g.plane) * sizeof(float);
+    // f(n) = P f*(n-1), exactly as the forward pull
+    float f[Q];
+    bool mk[Q], mv[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float v = *elem_rx(fprev, pb, i, src_row(n, i), src_x(n, i));
+      const U r = raw_bits<ST_F32>(v);
+      mk[i] = SOLIDS && i != 0 && (MOVING ? (r | 1u) == Storage<ST_F32>::kMoving
+                                         : r == Storage<ST_F32>::kRest);
+      mv[i] = MOVING && i != 0 && r == Storage<ST_F32>::kMoving;
+      f[i] = v;
+    }
+    if (SOLIDS) {
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        if (mk[i] && !solid) {
+          float v = *elem_rx(fprev, pb, D3Q19::opp[i], n.row[1][1], n.xn[1]);
+          if (MOVING && mv[i]) v += ph.Kw[i];
+          f[i] = v;
+        }
+    }
+    float lam[Q];
+    if (!SEED) {
+      // lambda^n = P^T nu^{n+1}: pull along +c_i
+      bool mb[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const uint8_t nf = (SOLIDS && i != 0) ? flags[src_foff(n, i)] : uint8_t(0);
-        bb[i] = nf & FLAG_SOLID;
-        mv[i] = ph.moving && bb[i] && (nf & FLAG_MOVING);
+        const float v = *elem_rx(nu1, pb, i, n.row[1 + D3Q19::cz[i]][1 + D3Q19::cy[i]],
+                                 n.xn[1 - D3Q19::cx[i]]);
+        mb[i] = SOLIDS && i != 0 && raw_bits<ST_F32>(v) == Storage<ST_F32>::kRest;
+        lam[i] = v;
       }
-      // recompute the pre-collision state f(n+1) = stream(f*(n))
-      float f[Q];
+      if (SOLIDS) {
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const float* p = fn + size_t(i) * g.plane + src_off(n, i);
-        if (SOLIDS && i != 0) p = bb[i] ? fn + size_t(D3Q19::opp[i]) * g.plane + n.own : p;
-        f[i] = *p;
-        if (SOLIDS && mv[i]) f[i] += ph.Kw[i];
+        for (int i = 1; i < Q; ++i)
+          if (mb[i] && !solid) lam[i] = *elem_rx(nu1, pb, D3Q19::opp[i], n.row[1][1], n.xn[1]);
       }
-      float lam[Q];
+    }
+    const bool forced = !(fl & FLAG_NOFORCE);
+    const float Fx = forced ? ph.F[0] : 0.0f, Fy = forced ? ph.F[1] : 0.0f,
+                Fz = forced ? ph.F[2] : 0.0f;
+    float drho, jx, jy, jz;
+    moments(f, drho, jx, jy, jz);
+    const bool inc = ph.incomp != 0;
+    const float rho = inc ? 1.0f : 1.0f + drho;  // the density dividing j' in u
+    const float inv_rho = inc ? 1.0f : 1.0f / rho;
+    const float ux = (jx + 0.5f * Fx) * inv_rho, uy = (jy + 0.5f * Fy) * inv_rho,
+                uz = (jz + 0.5f * Fz) * inv_rho;
+    if (SEED) {
+      // lambda^T_i = dL/drho + dL/du . (c_i - u)/rho  (dL/du . c_i when incompressible);
+      // u = (j + F/2)/rho of f(T) equals the velocity read from f*(T)
+      const float G = gr ? gr[n.fown] : 0.0f;
+      float hx = 0.0f, hy = 0.0f, hz = 0.0f;
+      if (gu) {
+        const size_t ncell = size_t(g.nx) * g.ny * g.nz;
+        hx = gu[n.fown] * inv_rho;
+        hy = gu[ncell + n.fown] * inv_rho;
+        hz = gu[2 * ncell + n.fown] * inv_rho;
+      }
+      const float base = inc ? G : G - (hx * ux + hy * uy + hz * uz);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) lam[i] = lam1[size_t(i) * g.plane + n.own];
-      const bool forced = !(fl & FLAG_NOFORCE);
-      const float Fx = forced ? ph.F[0] : 0.0f, Fy = forced ? ph.F[1] : 0.0f,
-                  Fz = forced ? ph.F[2] : 0.0f;
-      float drho, jx, jy, jz;
-      moments(f, drho, jx, jy, jz);
-      const bool inc = ph.incomp != 0;
-      const float rho = inc ? 1.0f : 1.0f + drho;  // the density dividing j' in u
-      const float inv_rho = inc ? 1.0f : 1.0f / rho;
-      const float ux = (jx + 0.5f * Fx) * inv_rho, uy = (jy + 0.5f * Fy) * inv_rho,
-                  uz = (jz + 0.5f * Fz) * inv_rho;
-      const float om = ph.omega, om1 = 1.0f - om, fpre = 1.0f - 0.5f * om;
-      const LamMoments m = lam_moments(lam);
-      // L2 u and L2 F
-      const float Lux = m.Lxx * ux + m.Lxy * uy + m.Lxz * uz;
-      const float Luy = m.Lxy * ux + m.Lyy * uy + m.Lyz * uz;
-      const float Luz = m.Lxz * ux + m.Lyz * uy + m.Lzz * uz;
-      const float LFx = m.Lxx * Fx + m.Lxy * Fy + m.Lxz * Fz;
-      const float LFy = m.Lxy * Fx + m.Lyy * Fy + m.Lyz * Fz;
-      const float LFz = m.Lxz * Fx + m.Lyz * Fy + m.Lzz * Fz;
-      const float uu = ux * ux + uy * uy + uz * uz;
-      const float a = inc ? om * m.L0
-                          : om * (m.L0 + 3.0f * (m.L1x * ux + m.L1y * uy + m.L1z * uz) +
-                                  4.5f * (ux * Lux + uy * Luy + uz * Luz) - 1.5f * uu * m.L0);
-      const float orho = om * rho;
-      const float bx = orho * (3.0f * m.L1x + 9.0f * Lux - 3.0f * ux * m.L0) +
-                       fpre * (9.0f * LFx - 3.0f * Fx * m.L0);
-      const float by = orho * (3.0f * m.L1y + 9.0f * Luy - 3.0f * uy * m.L0) +
-                       fpre * (9.0f * LFy - 3.0f * Fy * m.L0);
-      const float bz = orho * (3.0f * m.L1z + 9.0f * Luz - 3.0f * uz * m.L0) +
-                       fpre * (9.0f * LFz - 3.0f * Fz * m.L0);
-      const float bhx = bx * inv_rho, bhy = by * inv_rho, bhz = bz * inv_rho;
-      const float a0 = inc ? a : a - (bhx * ux + bhy * uy + bhz * uz);
-      // transposed streaming: push mu_i to the pull source of direction i
+      for (int i = 0; i < Q; ++i) lam[i] = base + cdot<float>(i, hx, hy, hz);
+      if (forced && !solid) {
+        d[0] = -double(hx) / 2.0;
+        d[1] = -double(hy) / 2.0;
+        d[2] = -double(hz) / 2.0;
+      }
+    }
+    const float om = ph.omega, om1 = 1.0f - om, fpre = 1.0f - 0.5f * om;
+    const LamMoments m = lam_moments(lam);
+    const float Lux = m.Lxx * ux + m.Lxy * uy + m.Lxz * uz;
+    const float Luy = m.Lxy * ux + m.Lyy * uy + m.Lyz * uz;
+    const float Luz = m.Lxz * ux + m.Lyz * uy + m.Lzz * uz;
+    const float LFx = m.Lxx * Fx + m.Lxy * Fy + m.Lxz * Fz;
+    const float LFy = m.Lxy * Fx + m.Lyy * Fy + m.Lyz * Fz;
+    const float LFz = m.Lxz * Fx + m.Lyz * Fy + m.Lzz * Fz;
+    const float uu = ux * ux + uy * uy + uz * uz;
+    const float a = inc ? om * m.L0
+                        : om * (m.L0 + 3.0f * (m.L1x * ux + m.L1y * uy + m.L1z * uz) +
+                                4.5f * (ux * Lux + uy * Luy + uz * Luz) - 1.5f * uu * m.L0);
+    const float orho = om * rho;
+    const float bx = orho * (3.0f * m.L1x + 9.0f * Lux - 3.0f * ux * m.L0) +
+                     fpre * (9.0f * LFx - 3.0f * Fx * m.L0);
+    const float by = orho * (3.0f * m.L1y + 9.0f * Luy - 3.0f * uy * m.L0) +
+                     fpre * (9.0f * LFy - 3.0f * Fy * m.L0);
+    const float bz = orho * (3.0f * m.L1z + 9.0f * Luz - 3.0f * uz * m.L0) +
+                     fpre * (9.0f * LFz - 3.0f * Fz * m.L0);
+    const float bhx = bx * inv_rho, bhy = by * inv_rho, bhz = bz * inv_rho;
+    const float a0 = inc ? a : a - (bhx * ux + bhy * uy + bhz * uz);
+    const float marker = from_bits<ST_F32>(Storage<ST_F32>::kRest);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const float mu = om1 * lam[i] + a0 + cdot<float>(i, bhx, bhy, bhz);
-        float* p = lam0 + size_t(i) * g.plane + src_off(n, i);
-        if (SOLIDS && i != 0) p = bb[i] ? lam0 + size_t(D3Q19::opp[i]) * g.plane + n.own : p;
-        *p = mu;
-      }
-      if (forced) {
-        d[0] = double(fpre * (3.0f * m.L1x - 3.0f * ux * m.L0 + 9.0f * Lux) + 0.5f * bhx);
-        d[1] = double(fpre * (3.0f * m.L1y - 3.0f * uy * m.L0 + 9.0f * Luy) + 0.5f * bhy);
-        d[2] = double(fpre * (3.0f * m.L1z - 3.0f * uz * m.L0 + 9.0f * Luz) + 0.5f * bhz);
-      }
+    for (int i = 0; i < Q; ++i) {
+      const float mu = om1 * lam[i] + a0 + cdot<float>(i, bhx, bhy, bhz);
+      stream_store(elem_rx(nu0, pb, i, n.row[1][1], n.xn[1]), solid ? marker : mu);
+    }
+    if (forced && !solid) {
+      d[0] += double(fpre * (3.0f * m.L1x - 3.0f * ux * m.L0 + 9.0f * Lux) + 0.5f * bhx);
+      d[1] += double(fpre * (3.0f * m.L1y - 3.0f * uy * m.L0 + 9.0f * Luy) + 0.5f * bhy);
+      d[2] += double(fpre * (3.0f * m.L1z - 3.0f * uz * m.L0 + 9.0f * Luz) + 0.5f * bhz);
     }
   }
   block_sum<3>(d, sh);
   if (threadIdx.x == 0)
-    for (int k = 0; k < 3; ++k) partials[size_t(l.lblock) * 3 + k] += d[k];
+    for (int k = 0; k < 3; ++k) {
+      if (SEED) partials[size_t(lb) * 3 + k] = d[k];
+      else partials[size_t(lb) * 3 + k] += d[k];
+    }
 }
 
-// dL/du0 = sum_i lam0_i w_i rho0 (3 c_i + 9 (c_i.u0) c_i - 3 u0) = rho0 (3 L1 + 9 L2 u0 - 3 u0 L0).
-// (rho0 -> 1 in the prefactor for the incompressible equilibrium.)
-__global__ __launch_bounds__(kBlock) void k_adj_init(const float* __restrict__ lam0,
+// dL/du0 = sum_i lam0_i w_i rho0 (3 c_i + 9 (c_i.u0) c_i - 3 u0) = rho0 (3 L1 + 9 L2 u0 - 3 u0 L0),
+// with lambda^0 = P^T nu^1 gathered along +c_i (rho0 -> 1 in the prefactor for
+// the incompressible equilibrium).
+template <bool SOLIDS>
+__global__ __launch_bounds__(kBlock) void k_adj_init(const float* __restrict__ nu1,
                                                      const uint8_t* __restrict__ flags,
                                                      const float* __restrict__ rho0,
                                                      const float* __restrict__ u0,
                                                      float* __restrict__ du0, Geo g, int incomp) {
   const Loc l = locate(g);
   if (!l.valid) return;
-  const uint32_t c = uint32_t((l.z * g.ny + l.y) * g.nx + l.x);
+  const Nbhd n = neighbourhood(g, l);
+  const uint32_t c = n.fown;
   const size_t ncell = size_t(g.nx) * g.ny * g.nz;
-  const uint32_t own = uint32_t(l.z * g.ny + l.y) * uint32_t(g.xs) + uint32_t(l.x);
   float rx = 0.0f, ry = 0.0f, rz = 0.0f;
-  if (!(flags && (flags[c] & FLAG_SOLID))) {
+  if (!(SOLIDS && (flags[c] & FLAG_SOLID))) {
+    const size_t pb = size_t(g.plane) * sizeof(float);
     float lam[Q];
+    bool mb[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) lam[i] = lam0[size_t(i) * g.plane + own];
+    for (int i = 0; i < Q; ++i) {
+      const float v = *elem_rx(nu1, pb, i, n.row[1 + D3Q19::cz[i]][1 + D3Q19::cy[i]],
+                               n.xn[1 - D3Q19::cx[i]]);
+      mb[i] = SOLIDS && i != 0 && raw_bits<ST_F32>(v) == Storage<ST_F32>::kRest;
+      lam[i] = v;
+    }
+    if (SOLIDS) {
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        if (mb[i]) lam[i] = *elem_rx(nu1, pb, D3Q19::opp[i], n.row[1][1], n.xn[1]);
+    }
     const LamMoments m = lam_moments(lam);
     const float rho = (rho0 && !incomp) ? rho0[c] : 1.0f;
     float ux = 0.0f, uy = 0.0f, uz = 0.0f;
@@ -1298,31 +1333,46 @@ hipError_t launch_reduce(int storage, const Geo& g, const PhysParams& ph, const 
   return hipGetLastError();
 }
 
-hipError_t launch_adj_seed(const Geo& g, const PhysParams& ph, const float* fT, const uint8_t* flags,
-                           const float* dL_drho, const float* dL_du, float* lam, double* partials,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_seed, dim3(g.nblocks), dim3(kBlock), 0, s, fT, flags, dL_drho, dL_du,
-                     lam, partials, g, float(ph.F[0]), float(ph.F[1]), float(ph.F[2]),
-                     ph.incomp ? 1 : 0);
-  return hipGetLastError();
-}
-
-hipError_t launch_adj_step(bool solids, const Geo& g, const PhysParams& ph, const float* fn,
-                           const uint8_t* flags, const float* lam_np1, float* lam_n,
-                           double* partials, hipStream_t s) {
-  if (solids)
-    hipLaunchKernelGGL(k_adj_step<true>, dim3(g.nblocks), dim3(kBlock), 0, s, fn, flags, lam_np1,
-                       lam_n, partials, g, to_phys<float>(ph));
+template <bool SEED>
+static void adj_t(bool solids, const Geo& g, const PhysParams& ph, const float* fprev,
+                  const float* nu1, float* nu0, const uint8_t* flags, const float* gr,
+                  const float* gu, double* partials, hipStream_t s) {
+  const Geo h = step_geo(g, 1);
+  const Phys<float> p = to_phys<float>(ph);
+  if (!solids)
+    hipLaunchKernelGGL((k_adj<false, false, SEED>), dim3(h.nblocks), dim3(kBlock), 0, s, fprev, nu1,
+                       nu0, flags, gr, gu, partials, h, p);
+  else if (!ph.moving)
+    hipLaunchKernelGGL((k_adj<true, false, SEED>), dim3(h.nblocks), dim3(kBlock), 0, s, fprev, nu1,
+                       nu0, flags, gr, gu, partials, h, p);
   else
-    hipLaunchKernelGGL(k_adj_step<false>, dim3(g.nblocks), dim3(kBlock), 0, s, fn, flags, lam_np1,
-                       lam_n, partials, g, to_phys<float>(ph));
+    hipLaunchKernelGGL((k_adj<true, true, SEED>), dim3(h.nblocks), dim3(kBlock), 0, s, fprev, nu1,
+                       nu0, flags, gr, gu, partials, h, p);
+}
+
+hipError_t launch_adj_seed(bool solids, const Geo& g, const PhysParams& ph, const float* fprev,
+                           const uint8_t* flags, const float* dL_drho, const float* dL_du,
+                           float* nu_T, double* partials, hipStream_t s) {
+  adj_t<true>(solids, g, ph, fprev, nullptr, nu_T, flags, dL_drho, dL_du, partials, s);
   return hipGetLastError();
 }
 
-hipError_t launch_adj_init(const Geo& g, const PhysParams& ph, const uint8_t* flags, const float* lam0,
-                           const float* rho0, const float* u0, float* dL_du0, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_init, dim3(g.nblocks), dim3(kBlock), 0, s, lam0, flags, rho0, u0,
-                     dL_du0, g, ph.incomp ? 1 : 0);
+hipError_t launch_adj_step(bool solids, const Geo& g, const PhysParams& ph, const float* fprev,
+                           const uint8_t* flags, const float* nu_np1, float* nu_n,
+                           double* partials, hipStream_t s) {
+  adj_t<false>(solids, g, ph, fprev, nu_np1, nu_n, flags, nullptr, nullptr, partials, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_init(bool solids, const Geo& g, const PhysParams& ph, const uint8_t* flags,
+                           const float* nu1, const float* rho0, const float* u0, float* dL_du0,
+                           hipStream_t s) {
+  if (solids)
+    hipLaunchKernelGGL(k_adj_init<true>, dim3(g.nblocks), dim3(kBlock), 0, s, nu1, flags, rho0, u0,
+                       dL_du0, g, ph.incomp ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_adj_init<false>, dim3(g.nblocks), dim3(kBlock), 0, s, nu1, flags, rho0, u0,
+                       dL_du0, g, ph.incomp ? 1 : 0);
   return hipGetLastError();
 }
 

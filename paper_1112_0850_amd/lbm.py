@@ -213,14 +213,17 @@ class _Rollout(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g_rho, g_u):
+        """Reverse sweep in pull form: nu^T from the seed at f*(T-1), then
+        nu^{m+1} from nu^{m+2} at f*(m) for m = T-2 .. 0, then dL/du0 from
+        nu^1; the f*(m) are recomputed segment by segment from the
+        checkpoints, latest segment first."""
         sim, ckpts, steps, k = ctx.sim, ctx.ckpts, ctx.steps, ctx.k
         dev = sim.device
         nfl = sim.grid_bytes // 4
-        lam = [torch.zeros(nfl, dtype=torch.float32, device=dev) for _ in range(2)]
-        partials = torch.zeros(sim.adj_partials_bytes // 8, dtype=torch.float64, device=dev)
+        nu = [torch.empty(nfl, dtype=torch.float32, device=dev) for _ in range(2)]
+        partials = torch.empty(sim.adj_partials_bytes // 8, dtype=torch.float64, device=dev)
         gr = None if g_rho is None else g_rho.to(torch.float32).contiguous()
         gu = None if g_u is None else g_u.to(torch.float32).contiguous()
-        A.lbm_adjoint_seed(sim.ctx, _ptr(gr), _ptr(gu), _ptr(lam[0]), _ptr(partials))
         cur = 0
         seg = [None] + [sim.new_grid() for _ in range(min(k, steps) - 1)]
         for s in range(len(ckpts) - 1, -1, -1):
@@ -228,12 +231,16 @@ class _Rollout(torch.autograd.Function):
             seg[0] = ckpts[s]
             for j in range(1, t1 - t0):
                 sim.step_from(seg[j - 1], seg[j])
-            for n in range(t1 - 1, t0 - 1, -1):
-                A.lbm_adjoint_step(sim.ctx, _ptr(seg[n - t0]), _ptr(lam[cur]), _ptr(lam[cur ^ 1]),
-                                   _ptr(partials))
-                cur ^= 1
+            for m in range(t1 - 1, t0 - 1, -1):  # f*(m) gives nu^{m+1}
+                if m == steps - 1:
+                    A.lbm_adjoint_seed(sim.ctx, _ptr(seg[m - t0]), _ptr(gr), _ptr(gu),
+                                       _ptr(nu[cur]), _ptr(partials))
+                else:
+                    A.lbm_adjoint_step(sim.ctx, _ptr(seg[m - t0]), _ptr(nu[cur]),
+                                       _ptr(nu[cur ^ 1]), _ptr(partials))
+                    cur ^= 1
         du0 = torch.empty((3,) + sim.shape, dtype=torch.float32, device=dev)
-        A.lbm_adjoint_init(sim.ctx, _ptr(lam[cur]), _ptr(sim.rho0), _ptr(sim.u0), _ptr(du0))
+        A.lbm_adjoint_init(sim.ctx, _ptr(nu[cur]), _ptr(sim.rho0), _ptr(sim.u0), _ptr(du0))
         dF = torch.empty(3, dtype=torch.float64, device=dev)
         A.lbm_adjoint_finish_dF(sim.ctx, _ptr(partials), _ptr(dF))
         gdt, gdev = ctx.g_meta

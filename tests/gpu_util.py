@@ -4,6 +4,8 @@ parity bars.  Test-side plumbing only (layout and dtype conversion)."""
 import numpy as np
 import torch
 
+from paper_1112_0850_amd import _abi as A
+
 from tests import lattice_ref as R
 
 W = R.e_w_opp()[1]
@@ -68,7 +70,6 @@ def check_solids(sim, flags, grid=None):
     marker for a moving-wall cell when the wall velocity is not zero, else
     the resting one) and no fluid slot does; fluid values are finite.
     Returns the offsets with solid cells zeroed (the oracle's convention)."""
-    from paper_1112_0850_amd import _abi as A
     rest, mov = A.lbm_solid_markers(sim.storage)
     bits = raw_bits(sim, grid)
     solid = (flags & 1) == 1
@@ -80,6 +81,37 @@ def check_solids(sim, flags, grid=None):
     assert np.isfinite(g[:, ~solid]).all(), "non-finite fluid population"
     g[:, solid] = 0.0
     return g
+
+
+def to_nu_grid(sim, nu, flags=None):
+    """float64 [19, nz, ny, nx] -> zero-padded FP32 buffer in the grid layout
+    holding an adjoint state nu = dL/df; solid cells get the resting marker
+    (what the adjoint kernels leave there)."""
+    nz, ny, nx = sim.shape
+    buf = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
+    v = sim.grid_view(buf)
+    v[..., :nx].copy_(torch.from_numpy(nu).float())
+    if flags is not None:
+        rest, _ = A.lbm_solid_markers(A.LBM_F32)
+        bits = sim.grid_view(buf.view(torch.int32))[..., :nx]
+        solid = torch.from_numpy((flags & 1) == 1).cuda()
+        bits[:, solid] = np.int32(np.uint32(rest).view(np.int32))
+    return buf
+
+
+def from_nu_grid(sim, buf, flags=None):
+    """The fluid values of an adjoint grid as float64 [19, nz, ny, nx] (solid
+    cells 0), after checking that every solid slot holds the marker."""
+    nz, ny, nx = sim.shape
+    v = sim.grid_view(buf)[..., :nx].double().cpu().numpy()
+    if flags is not None:
+        rest, _ = A.lbm_solid_markers(A.LBM_F32)
+        bits = sim.grid_view(buf.view(torch.int32))[..., :nx].cpu().numpy().view(np.uint32)
+        solid = (flags & 1) == 1
+        assert (bits[:, solid] == rest).all(), "adjoint marker missing"
+        assert np.isfinite(v[:, ~solid]).all()
+        v[:, solid] = 0.0
+    return v
 
 
 def rel_linf(a, b, mask=None):

@@ -12,7 +12,7 @@ from oracle import oracle as O
 from paper_1112_0850_amd import _abi as A
 from paper_1112_0850_amd import inputs as I
 from paper_1112_0850_amd.lbm import LBM, rollout
-from tests.gpu_util import f_to_grid, grid_to_f, rel_linf, say
+from tests.gpu_util import f_to_grid, from_nu_grid, grid_to_f, rel_linf, say, to_nu_grid
 from tests.test_oracle_adjoint import rollout_grad, rollout_loss
 
 pytestmark = pytest.mark.gpu
@@ -21,21 +21,6 @@ P = lambda t: None if t is None else ctypes.c_void_p(t.data_ptr())
 
 def _f32(a):
     return np.asarray(a, dtype=np.float32).astype(np.float64)
-
-
-def _to_lam_grid(sim, lam):
-    """float64 [19, nz, ny, nx] -> zero-padded FP32 buffer in the grid layout."""
-    nz, ny, nx = sim.shape
-    buf = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
-    v = sim.grid_view(buf)
-    v[..., :nx].copy_(torch.from_numpy(lam).float())
-    return buf
-
-
-def _from_lam_grid(sim, buf):
-    nz, ny, nx = sim.shape
-    v = sim.grid_view(buf)
-    return v[..., :nx].double().cpu().numpy()
 
 
 @pytest.fixture(scope="module")
@@ -47,9 +32,9 @@ def case():
     u0[:, flags & 1 == 1] = 0
     tau, F = 0.62, (3e-4, -2e-4, 1e-4)
     fn = O.step(O.init(shape, flags, None, _f32(u0)), tau, F, flags, n=3)
-    lam1 = rng.standard_normal((19,) + shape)
-    lam1[:, flags & 1 == 1] = 0
-    return dict(shape=shape, flags=flags, tau=tau, F=F, fn=fn, lam1=_f32(lam1), u0=_f32(u0))
+    nu1 = rng.standard_normal((19,) + shape)
+    nu1[:, flags & 1 == 1] = 0
+    return dict(shape=shape, flags=flags, tau=tau, F=F, fn=fn, nu1=_f32(nu1), u0=_f32(u0))
 
 
 def _sim(c):
@@ -57,50 +42,59 @@ def _sim(c):
 
 
 def test_adjoint_step_kernel_vs_oracle(case):
+    """nu^n = J(f(n))^T P^T nu^{n+1} with f(n) = P f*(n-1): the kernel against
+    the oracle's transposed streaming and transposed collision."""
     say("adjoint step kernel vs oracle", case["shape"])
-    sim = _sim(case)
-    f_to_grid(sim, case["fn"], flags=case["flags"])
-    fn32 = grid_to_f(sim)  # the FP32-rounded state the kernel sees
-    lam1 = _to_lam_grid(sim, case["lam1"])
-    lam0 = torch.zeros_like(lam1)
+    sim, fl = _sim(case), case["flags"]
+    f_to_grid(sim, case["fn"], flags=fl)
+    fprev = grid_to_f(sim)  # the FP32-rounded f*(n-1) the kernel sees
+    nu1 = to_nu_grid(sim, case["nu1"], fl)
+    nu0 = torch.zeros_like(nu1)
     part = torch.zeros(sim.adj_partials_bytes // 8, dtype=torch.float64, device="cuda")
-    A.lbm_adjoint_step(sim.ctx, P(sim.grids[sim.current]), P(lam1), P(lam0), P(part))
+    A.lbm_adjoint_step(sim.ctx, P(sim.grids[sim.current]), P(nu1), P(nu0), P(part))
     dF = torch.empty(3, dtype=torch.float64, device="cuda")
     A.lbm_adjoint_finish_dF(sim.ctx, P(part), P(dF))
     torch.cuda.synchronize()
-    ref, dF_ref = O.adjoint_step(fn32, case["lam1"], case["tau"], case["F"], case["flags"])
-    got = _from_lam_grid(sim, lam0)
+    lam = O.stream_transpose(case["nu1"], fl)
+    ref, dF_ref = O.adjoint_collide(O.stream(fprev, fl), lam, case["tau"], case["F"], fl)
+    got = from_nu_grid(sim, nu0, fl)
     e = rel_linf(got, ref)
     eF = np.abs(dF.cpu().numpy() - dF_ref).max() / np.abs(dF_ref).max()
-    say(f"  lambda rel L-inf {e:.2e}, dL/dF rel {eF:.2e}")
+    say(f"  nu rel L-inf {e:.2e}, dL/dF rel {eF:.2e}")
     assert e <= 1e-5 and eF <= 1e-5
-    assert not got[:, case["flags"] & 1 == 1].any()
 
 
 def test_adjoint_seed_and_init_kernels_vs_oracle(case):
+    """Seed: nu^T = J(f(T))^T lambda^T with lambda^T from dL/drho_T, dL/du_T
+    (f(T) = P f*(T-1); the oracle forms lambda^T from f*(T)) and the dL/dF
+    terms of both; init: dL/du0 from lambda^0 = P^T nu^1."""
     say("adjoint seed/init kernels vs oracle")
-    sim = _sim(case)
-    f_to_grid(sim, case["fn"], flags=case["flags"])
-    fT = grid_to_f(sim)
+    sim, fl = _sim(case), case["flags"]
+    f_to_grid(sim, case["fn"], flags=fl)
+    fprev = grid_to_f(sim)
     rng = np.random.default_rng(8)
     shape = case["shape"]
     gr, gu = _f32(rng.standard_normal(shape)), _f32(rng.standard_normal((3,) + shape))
-    lam = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
+    nu = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
     part = torch.zeros(sim.adj_partials_bytes // 8, dtype=torch.float64, device="cuda")
     grt, gut = torch.from_numpy(gr).float().cuda(), torch.from_numpy(gu).float().cuda()
-    A.lbm_adjoint_seed(sim.ctx, P(grt), P(gut), P(lam), P(part))
+    A.lbm_adjoint_seed(sim.ctx, P(sim.grids[sim.current]), P(grt), P(gut), P(nu), P(part))
     dF = torch.empty(3, dtype=torch.float64, device="cuda")
     A.lbm_adjoint_finish_dF(sim.ctx, P(part), P(dF))
-    lam_ref, dF_ref = O.adjoint_seed(fT, gr, gu, case["F"], case["flags"])
+    tau, F = case["tau"], case["F"]
+    lam_ref, dF1 = O.adjoint_seed(O.step(fprev, tau, F, fl), gr, gu, F, fl)
+    nu_ref, dF2 = O.adjoint_collide(O.stream(fprev, fl), lam_ref, tau, F, fl)
     torch.cuda.synchronize()
-    assert rel_linf(_from_lam_grid(sim, lam), lam_ref) <= 1e-6
-    assert np.abs(dF.cpu().numpy() - dF_ref).max() <= 1e-6 * np.abs(dF_ref).max()
-    # init: dL/du0 from lambda^0 at (rho0 = 1, u0)
-    lam0 = _to_lam_grid(sim, case["lam1"])
+    e = rel_linf(from_nu_grid(sim, nu, fl), nu_ref)
+    eF = np.abs(dF.cpu().numpy() - (dF1 + dF2)).max() / np.abs(dF1 + dF2).max()
+    say(f"  seed: nu rel L-inf {e:.2e}, dL/dF rel {eF:.2e}")
+    assert e <= 1e-5 and eF <= 1e-5
+    # init: dL/du0 from lambda^0 = P^T nu^1 at (rho0 = 1, u0)
+    nu1 = to_nu_grid(sim, case["nu1"], fl)
     u0t = torch.from_numpy(case["u0"]).float().cuda()
     du0 = torch.empty((3,) + shape, dtype=torch.float32, device="cuda")
-    A.lbm_adjoint_init(sim.ctx, P(lam0), None, P(u0t), P(du0))
-    ref, _ = O.adjoint_init(case["lam1"], case["u0"], case["flags"])
+    A.lbm_adjoint_init(sim.ctx, P(nu1), None, P(u0t), P(du0))
+    ref, _ = O.adjoint_init(O.stream_transpose(case["nu1"], fl), case["u0"], fl)
     torch.cuda.synchronize()
     assert rel_linf(du0.double().cpu().numpy(), ref) <= 1e-6
 

@@ -65,7 +65,7 @@ def test_adjoint_rejects_unsupported_storage(storage):
     lam = torch.zeros(sim.grid_bytes // 4 + 64, dtype=torch.float32, device="cuda")
     part = torch.zeros(sim.adj_partials_bytes // 8, dtype=torch.float64, device="cuda")
     with pytest.raises(A.LBMError) as e:
-        A.lbm_adjoint_seed(sim.ctx, None, None, P(lam), P(part))
+        A.lbm_adjoint_seed(sim.ctx, P(sim.grids[sim.current]), None, None, P(lam), P(part))
     assert e.value.status == A.LBM_E_UNSUPPORTED
 
 

@@ -223,28 +223,33 @@ def test_sampled_step_at_maximum_size():
 
 
 def test_sampled_adjoint_step_at_rollout_size():
+    """The pull-form adjoint step at the rollout's 128^3 size: nu^n at sampled
+    cells against the oracle's transposed streaming and transposed collision
+    on the cell's 5^3 neighbourhood (periodic crops; the centre depends on
+    its 3^3 neighbours only)."""
     n = 128
     say(f"adjoint kernel at {n}^3: sampled parity on 5^3 neighbourhoods")
     u0 = torch.from_numpy(I.smooth_field(n, 2024, amplitude=0.02))
     sim = LBM((n, n, n), 0.6, (1e-6, 0, 0), "f32", u0=u0)
     sim.step(5)
     rng = np.random.default_rng(6)
-    lam1 = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
-    v1 = sim.grid_view(lam1)
+    nu1 = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
+    v1 = sim.grid_view(nu1)
     v1[..., :n].copy_(torch.from_numpy(rng.standard_normal((19, n, n, n)).astype(np.float32)))
-    lam0 = torch.zeros_like(lam1)
+    nu0 = torch.zeros_like(nu1)
     part = torch.zeros(sim.adj_partials_bytes // 8, dtype=torch.float64, device="cuda")
     P = lambda t: ctypes.c_void_p(t.data_ptr())
-    A.lbm_adjoint_step(sim.ctx, P(sim.grids[sim.current]), P(lam1), P(lam0), P(part))
+    A.lbm_adjoint_step(sim.ctx, P(sim.grids[sim.current]), P(nu1), P(nu0), P(part))
     torch.cuda.synchronize()
-    v0 = sim.grid_view(lam0)
+    v0 = sim.grid_view(nu0)
     fv = sim.populations()
     worst = 0.0
-    for _ in range(64):
-        z, y, x = (int(v) for v in rng.integers(0, n, size=3))
+    zyx = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 63), (n - 1, 0, 64)]
+    zyx += [tuple(int(v) for v in rng.integers(0, n, size=3)) for _ in range(60)]
+    for z, y, x in zyx:
         f = _crop(fv, z, y, x, 2, n, n, n).double().cpu().numpy() + W[:, None, None, None]
         l1 = _crop(v1, z, y, x, 2, n, n, n).double().cpu().numpy()
-        ref, _ = O.adjoint_step(f, l1, 0.6, (1e-6, 0, 0), None)
+        ref, _ = O.adjoint_collide(O.stream(f), O.stream_transpose(l1), 0.6, (1e-6, 0, 0))
         got = v0[:, z, y, x].double().cpu().numpy()
         e = np.abs(got - ref[:, 2, 2, 2]).max() / np.abs(ref[:, 2, 2, 2]).max()
         worst = max(worst, e)

@@ -16,7 +16,7 @@ from oracle import oracle as O
 from paper_1112_0850_amd import _abi as A
 from paper_1112_0850_amd import inputs as I
 from paper_1112_0850_amd.lbm import LBM, rollout
-from tests.gpu_util import check_solids, f_to_grid, grid_to_f, rel_linf, say
+from tests.gpu_util import from_nu_grid, to_nu_grid, check_solids, f_to_grid, grid_to_f, rel_linf, say
 from tests.test_gpu_forward import _round_to
 from tests.test_oracle_adjoint import rollout_grad
 
@@ -180,24 +180,11 @@ def test_incompressible_porous_moving_walls_parity(storage, s, tol):
 
 # -- adjoint with both options ------------------------------------------------
 
-def _to_lam_grid(sim, lam):
-    nz, ny, nx = sim.shape
-    buf = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
-    v = sim.grid_view(buf)
-    v[..., :nx].copy_(torch.from_numpy(lam).float())
-    return buf
-
-
-def _from_lam_grid(sim, buf):
-    nz, ny, nx = sim.shape
-    v = sim.grid_view(buf)
-    return v[..., :nx].double().cpu().numpy()
-
-
 @pytest.mark.parametrize("inc", [False, True])
 def test_adjoint_kernels_vs_oracle(inc):
-    """Seed, step and init kernels with moving walls and the chosen
-    equilibrium against the oracle's reverse-mode functions."""
+    """Seed, step and init kernels (pull form: nu = dL/df is carried) with
+    moving walls and the chosen equilibrium against the oracle's transposed
+    streaming and transposed collision."""
     shape, tau, F, uw = (9, 10, 70), 0.62, (3e-4, -2e-4, 1e-4), (0.04, 0.0, 0.01)
     say("adjoint kernels, moving walls, incompressible =", inc)
     flags = _moving_flags(shape, 55)
@@ -206,42 +193,48 @@ def test_adjoint_kernels_vs_oracle(inc):
     u0[:, flags & 1 == 1] = 0
     fn = O.step(O.init(shape, flags, None, u0, incompressible=inc), tau, F, flags, n=3, wall_u=uw,
                 incompressible=inc)
-    lam1 = _f32(rng.standard_normal((19,) + shape))
-    lam1[:, flags & 1 == 1] = 0
+    nu1 = _f32(rng.standard_normal((19,) + shape))
+    nu1[:, flags & 1 == 1] = 0
     eq = "incompressible" if inc else "qian"
     sim = LBM(shape, tau, F, "f32", flags=flags, wall_u=uw, equilibrium=eq)
     f_to_grid(sim, fn, flags=flags)
-    fn32 = grid_to_f(sim)
+    fprev = grid_to_f(sim)
+    f_pre = O.stream(fprev, flags, wall_u=uw)
     # step
-    lt1 = _to_lam_grid(sim, lam1)
-    lt0 = torch.zeros_like(lt1)
+    nt1 = to_nu_grid(sim, nu1, flags)
+    nt0 = torch.zeros_like(nt1)
     part = torch.zeros(sim.adj_partials_bytes // 8, dtype=torch.float64, device="cuda")
-    A.lbm_adjoint_step(sim.ctx, P(sim.grids[sim.current]), P(lt1), P(lt0), P(part))
+    A.lbm_adjoint_step(sim.ctx, P(sim.grids[sim.current]), P(nt1), P(nt0), P(part))
     dF = torch.empty(3, dtype=torch.float64, device="cuda")
     A.lbm_adjoint_finish_dF(sim.ctx, P(part), P(dF))
     torch.cuda.synchronize()
-    ref, dF_ref = O.adjoint_step(fn32, lam1, tau, F, flags, wall_u=uw, incompressible=inc)
-    e, eF = rel_linf(_from_lam_grid(sim, lt0), ref), np.abs(dF.cpu().numpy() - dF_ref).max() / \
+    ref, dF_ref = O.adjoint_collide(f_pre, O.stream_transpose(nu1, flags), tau, F, flags,
+                                    incompressible=inc)
+    e, eF = rel_linf(from_nu_grid(sim, nt0, flags), ref), np.abs(dF.cpu().numpy() - dF_ref).max() / \
         np.abs(dF_ref).max()
-    say(f"  step: lambda {e:.2e}, dL/dF {eF:.2e}")
+    say(f"  step: nu {e:.2e}, dL/dF {eF:.2e}")
     assert e <= 1e-5 and eF <= 1e-5
     # seed
     gr, gu = _f32(rng.standard_normal(shape)), _f32(rng.standard_normal((3,) + shape))
     grt, gut = torch.from_numpy(gr).float().cuda(), torch.from_numpy(gu).float().cuda()
-    lam = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
-    part.zero_()
-    A.lbm_adjoint_seed(sim.ctx, P(grt), P(gut), P(lam), P(part))
+    nu = torch.zeros(sim.grid_bytes // 4, dtype=torch.float32, device="cuda")
+    A.lbm_adjoint_seed(sim.ctx, P(sim.grids[sim.current]), P(grt), P(gut), P(nu), P(part))
     A.lbm_adjoint_finish_dF(sim.ctx, P(part), P(dF))
-    lam_ref, dFs_ref = O.adjoint_seed(fn32, gr, gu, F, flags, incompressible=inc)
+    fT = O.step(fprev, tau, F, flags, wall_u=uw, incompressible=inc)
+    lam_ref, dF1 = O.adjoint_seed(fT, gr, gu, F, flags, incompressible=inc)
+    nu_ref, dF2 = O.adjoint_collide(f_pre, lam_ref, tau, F, flags, incompressible=inc)
     torch.cuda.synchronize()
-    assert rel_linf(_from_lam_grid(sim, lam), lam_ref) <= 1e-6
-    assert np.abs(dF.cpu().numpy() - dFs_ref).max() <= 1e-6 * np.abs(dFs_ref).max()
+    e, eF = rel_linf(from_nu_grid(sim, nu, flags), nu_ref), \
+        np.abs(dF.cpu().numpy() - (dF1 + dF2)).max() / np.abs(dF1 + dF2).max()
+    say(f"  seed: nu {e:.2e}, dL/dF {eF:.2e}")
+    assert e <= 1e-5 and eF <= 1e-5
     # init, with a non-uniform rho0
     rho0 = _f32(1 + 0.02 * (rng.random(shape) - 0.5))
     du0 = torch.empty((3,) + shape, dtype=torch.float32, device="cuda")
     rho0t, u0t = torch.from_numpy(rho0).float().cuda(), torch.from_numpy(u0).float().cuda()
-    A.lbm_adjoint_init(sim.ctx, P(lt1), P(rho0t), P(u0t), P(du0))
-    ref, _ = O.adjoint_init(lam1, u0, flags, rho0=rho0, incompressible=inc)
+    A.lbm_adjoint_init(sim.ctx, P(nt1), P(rho0t), P(u0t), P(du0))
+    ref, _ = O.adjoint_init(O.stream_transpose(nu1, flags), u0, flags, rho0=rho0,
+                            incompressible=inc)
     torch.cuda.synchronize()
     assert rel_linf(du0.double().cpu().numpy(), ref) <= 1e-6
 
