@@ -507,7 +507,7 @@ KERNELS = {  # record key -> (kernel name, box edge, bytes per fluid update, por
     "bf16": ("void lbm::k_step<2, 1, true, false, 4>", 512, 76, True),
     "f64": ("void lbm::k_step<3, 1, true, false, 1>", 512, 304, True),
     "f32x": ("void lbm::k_step<4, 1, true, false, 1>", 512, 152, True),
-    "adjoint": ("void lbm::k_adj_step<false>", 256, 228, False),  # periodic, no flags
+    "adjoint": ("void lbm::k_adj<false, false, false>", 256, 228, False),  # periodic, no flags
 }
 
 

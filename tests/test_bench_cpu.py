@@ -64,7 +64,7 @@ def test_launch_geometry_identifies_the_box():
     assert b.launch_threads(f32, 512) == 512 ** 3  # 64-cell runs, 4 per 256-thread block
     assert b.launch_threads(f16, 512) == 512 ** 3 // 4  # 4 cells per lane
     assert b.box_of(f32, 768 ** 3) == 768 and b.box_of(f16, 512 ** 3 // 4) == 512
-    assert b.box_of("void lbm::k_adj_step<false>", 256 ** 3) == 256
+    assert b.box_of("void lbm::k_adj<false, false, false>", 256 ** 3) == 256
     assert b.box_of(f32, 12345) is None
 
 
