@@ -501,19 +501,28 @@ def traffic_record(key):
     return t.get("kernels", {}).get(key)
 
 
-KERNELS = {  # record key -> (kernel name, box edge, bytes per fluid update, porous 512 geometry)
-    "f32": ("void lbm::k_step<0, 1, true, false, 1>", 512, 152, True),
-    "f16": ("void lbm::k_step<1, 1, true, false, 4>", 512, 76, True),
-    "bf16": ("void lbm::k_step<2, 1, true, false, 4>", 512, 76, True),
-    "f64": ("void lbm::k_step<3, 1, true, false, 1>", 512, 304, True),
-    "f32x": ("void lbm::k_step<4, 1, true, false, 1>", 512, 152, True),
-    "adjoint": ("void lbm::k_adj<false, false, false>", 256, 228, False),  # periodic, no flags
+KERNELS = {  # record key -> (kernel name, box edge, bytes per fluid update, porous 512 geometry,
+             #                steps per launch)
+    "f32": ("void lbm::k_step<0, 1, true, false, 1>", 512, 152, True, 1),
+    "f16": ("void lbm::k_step<1, 1, true, false, 4>", 512, 76, True, 1),
+    "bf16": ("void lbm::k_step<2, 1, true, false, 4>", 512, 76, True, 1),
+    "f64": ("void lbm::k_step<3, 1, true, false, 1>", 512, 304, True, 1),
+    "f32x": ("void lbm::k_step<4, 1, true, false, 1>", 512, 152, True, 1),
+    "f32x2": ("void lbm::k_step2<0, 1, true, false>", 512, 152, True, 2),
+    "f16x2": ("void lbm::k_step2<1, 1, true, false>", 512, 76, True, 2),
+    "adjoint": ("void lbm::k_adj<false, false, false>", 256, 228, False, 1),  # periodic, no flags
 }
 
 
 def launch_threads(name, n):
     """Threads a launch of the named kernel has on an n^3 box (64 * M-cell
-    segments per row, four per block, M = 4 for the 16-bit step kernels)."""
+    segments per row, four per block, M = 4 for the 16-bit step kernels; the
+    two-step kernel: 64 x TY tiles (TY = 8, 13 for 16-bit, 4 for FP64) and
+    128-plane z chunks, 64 (TY + 3) threads per block)."""
+    if name.startswith("void lbm::k_step2<"):
+        k = int(name.split("<")[1].split(",")[0])
+        ty = {1: 13, 2: 13, 3: 4}.get(k, 8)
+        return -(-n // 64) * -(-n // ty) * -(-n // min(n, 128)) * 64 * (ty + 3)
     m = 4 if name.startswith("void lbm::k_step<1,") or name.startswith("void lbm::k_step<2,") else 1
     nseg = -(-n // (64 * m))
     return -(-nseg * n * n // 4) * 256
@@ -563,15 +572,15 @@ def profile_summary(trace_dir, fetch_dir, write_dir, n=512):
         avg_us = float(np.mean(v))
         box = box_of(name, grid) if name.startswith("void lbm::k_") else None
         row = [name.replace("void ", "")[:44], f"{box}^3" if box else "", str(len(v)), f"{avg_us:.1f}"]
-        rec_key = next((k for k, (kn, kb, _, _) in KERNELS.items() if kn == name and kb == box), None)
+        rec_key = next((k for k, (kn, kb, _, _, _) in KERNELS.items() if kn == name and kb == box), None)
         fk, wk = (name, grid, "FETCH_SIZE"), (name, grid, "WRITE_SIZE")
         if fk in counters and wk in counters:
             fb = float(np.mean(counters[fk])) * 1024 * scale["FETCH_SIZE"]
             wb = float(np.mean(counters[wk])) * 1024 * scale["WRITE_SIZE"]
             row += [f"{fb / 1e9:.2f}", f"{wb / 1e9:.2f}"]
             if rec_key:
-                _, kb, bpu, porous = KERNELS[rec_key]
-                alg = bpu * n_fluid + n ** 3 if porous else bpu * kb ** 3
+                _, kb, bpu, porous, nst = KERNELS[rec_key]
+                alg = nst * (bpu * n_fluid + n ** 3 if porous else bpu * kb ** 3)
                 row += [f"{alg / 1e9:.2f}", f"{(fb + wb) / alg:.3f}", f"{(fb + wb) / avg_us / 1e6:.2f}"]
                 record[rec_key] = {"kernel": name, "box": box, "avg_us": avg_us, "fetch_bytes": fb,
                                    "write_bytes": wb, "alg_bytes": alg}
@@ -654,6 +663,7 @@ def main():
         return sweep(torch)
 
     legs = set(args.only.split(",")) if args.only else {"f32", "f16", "bf16", "f64", "f32x",
+                                                        "f32x2", "f16x2", "bf16x2",
                                                         "adjoint", "copy", "cpu", "large", "cavity",
                                                         "split", "incomp"}
     n = args.n
@@ -694,6 +704,15 @@ def main():
         del fluid, rho32, u32
     fields.clear()
     torch.cuda.empty_cache()
+    if legs & {"f32x2", "f16x2", "bf16x2"}:
+        # the same workload with pairs of steps fused into one temporally blocked pass
+        for st, s in (("f32", 0), ("f16", 12), ("bf16", 0)):
+            if f"{st}x2" in legs:
+                log(f"forward {st}, two steps per pass")
+                res[f"{st}x2"] = forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st, args.steps,
+                                             args.warmup, s, steps_per_pass=2)
+                log(f"  {res[f'{st}x2']['mlups']:.0f} MLUPS, {res[f'{st}x2']['alg_gbs']:.0f} GB/s "
+                    "algorithmic")
     if "split" in legs:
         # the paper's split design: a separate obstacle kernel before each step
         log("split design (separate obstacle kernel), f32 and f16")
@@ -780,6 +799,9 @@ def main():
         line["cavity"] = res["cavity"]
     if "split" in res:
         line["split_obstacle_kernel"] = res["split"]
+    for st in ("f32", "f16", "bf16"):
+        if f"{st}x2" in res:
+            line[f"{st}_two_steps_per_pass"] = res[f"{st}x2"]
     if "incomp" in res:
         line["incompressible_equilibrium"] = res["incomp"]
     if "error_vs_oracle" in res:

@@ -147,6 +147,13 @@ typedef struct {
                               of the source grid before each step (for the
                               measured comparison; with it lbm_step_from
                               rewrites the solid-cell slots of src) */
+  int32_t steps_per_pass; /* 0 or 1: one step per kernel pass; 2: lbm_step
+                             runs pairs of steps as one fused pass that keeps
+                             the intermediate level on chip (temporal
+                             blocking along z, half the HBM traffic of two
+                             passes), bit-identical to single steps; an odd
+                             remainder is one single step.  Not with
+                             obstacle_kernel = 1 (LBM_E_UNSUPPORTED). */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -199,7 +206,8 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* grid_a, void* grid
 
 /* Enqueues n >= 0 fused stream-collide steps (pull streaming with half-way
  * bounce-back, moments, equilibrium, BGK relaxation with Guo forcing: Sec. 2
- * steps 1-3, Eq. (1)), alternating between the two grids.
+ * steps 1-3, Eq. (1)), alternating between the two grids (each kernel pass
+ * writes the other grid: one step, or two with steps_per_pass = 2).
  * Errors: LBM_E_ARG (NULL ctx, n < 0), LBM_E_HIP (launch failure). */
 lbm_status lbm_step(lbm_ctx* ctx, int32_t n);
 

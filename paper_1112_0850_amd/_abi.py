@@ -23,7 +23,8 @@ class lbm_params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("storage", C.c_int32), ("f16_scale_log2", C.c_int32), ("x_align", C.c_int32),
                 ("tau", C.c_double), ("force", C.c_double * 3), ("wall_u", C.c_double * 3),
-                ("equilibrium", C.c_int32), ("obstacle_kernel", C.c_int32)]
+                ("equilibrium", C.c_int32), ("obstacle_kernel", C.c_int32),
+                ("steps_per_pass", C.c_int32)]
 
 
 class LBMError(RuntimeError):
@@ -94,7 +95,7 @@ def check(status):
 
 
 def params(shape, tau, force=(0.0, 0.0, 0.0), storage=LBM_F32, f16_scale_log2=0, x_align=0,
-           wall_u=(0.0, 0.0, 0.0), equilibrium=LBM_EQ_QIAN, obstacle_kernel=0):
+           wall_u=(0.0, 0.0, 0.0), equilibrium=LBM_EQ_QIAN, obstacle_kernel=0, steps_per_pass=0):
     nz, ny, nx = shape
     p = lbm_params()
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
@@ -107,6 +108,7 @@ def params(shape, tau, force=(0.0, 0.0, 0.0), storage=LBM_F32, f16_scale_log2=0,
         p.wall_u[d] = float(wall_u[d])
     p.equilibrium = int(equilibrium)
     p.obstacle_kernel = int(obstacle_kernel)
+    p.steps_per_pass = int(steps_per_pass)
     return p
 
 

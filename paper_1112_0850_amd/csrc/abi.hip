@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -18,6 +19,8 @@
 #include "d3q19.h"
 #include "kernels.h"
 
+static_assert(sizeof(lbm_params) == 96 && offsetof(lbm_params, steps_per_pass) == 88,
+              "lbm_params layout changed: update the bindings");
 static_assert(lbm::Storage<lbm::ST_F32>::kRest == LBM_MARK_F32_REST &&
                   lbm::Storage<lbm::ST_F32>::kMoving == LBM_MARK_F32_MOVING &&
                   lbm::Storage<lbm::ST_F32X>::kRest == LBM_MARK_F32_REST &&
@@ -92,6 +95,10 @@ lbm_status check_params(const lbm_params* p, Sizes* sz) {
     return fail(LBM_E_ARG, "unknown equilibrium %d", p->equilibrium);
   if (p->obstacle_kernel != 0 && p->obstacle_kernel != 1)
     return fail(LBM_E_ARG, "obstacle_kernel must be 0 or 1 (got %d)", p->obstacle_kernel);
+  if (p->steps_per_pass < 0 || p->steps_per_pass > 2)
+    return fail(LBM_E_ARG, "steps_per_pass must be 0, 1 or 2 (got %d)", p->steps_per_pass);
+  if (p->steps_per_pass == 2 && p->obstacle_kernel == 1)
+    return fail(LBM_E_UNSUPPORTED, "two steps per pass are not available with the obstacle kernel");
   if (p->storage == LBM_F16 && (p->f16_scale_log2 < -24 || p->f16_scale_log2 > 24))
     return fail(LBM_E_ARG, "f16_scale_log2 must be in [-24, 24] (got %d)", p->f16_scale_log2);
   if (p->x_align < 0 || p->x_align > 4096)
@@ -170,6 +177,7 @@ struct lbm_ctx {
   int64_t t;
   bool force;
   int32_t graph_steps;         // 0: one launch per step; else replay graphs of this many steps
+  int graph_end[2];            // grid that holds the latest level after a replay from grid p
   hipGraphExec_t graph[2];     // per starting grid, captured by lbm_use_graphs
   hipStream_t capture_stream;  // library-owned, used only to capture the graphs
   hipEvent_t replay_done;      // recorded after the latest graph replay
@@ -201,6 +209,31 @@ lbm_status launch_steps(lbm_ctx* c, const void* src, void* dst) {
   return launch_steps_on(c, src, dst, c->stream);
 }
 
+// Enqueues n steps from grid *cur on stream s, two fused steps per pass when
+// the context asks for it (each pass writes the other grid, like one single
+// step); *cur becomes the grid that holds the latest enqueued level and
+// *done the number of steps enqueued (all n unless a launch failed).
+lbm_status enqueue_steps(lbm_ctx* c, int32_t n, int* cur, hipStream_t s, int32_t* done) {
+  *done = 0;
+  while (n > 0) {
+    const int k = *cur;
+    if (c->p.steps_per_pass == 2 && n >= 2) {
+      hipError_t e = lbm::launch_step2(c->p.storage, c->flags != nullptr, c->force, c->geo, c->ph,
+                                       c->grid[k], c->grid[k ^ 1], c->flags, s);
+      if (e != hipSuccess) return hip_fail(e, "two-step launch");
+      n -= 2;
+      *done += 2;
+    } else {
+      lbm_status st = launch_steps_on(c, c->grid[k], c->grid[k ^ 1], s);
+      if (st != LBM_OK) return st;
+      n -= 1;
+      *done += 1;
+    }
+    *cur = k ^ 1;
+  }
+  return LBM_OK;
+}
+
 // Waits for the latest replay (through its event, valid whatever became of
 // the stream it was queued on), then destroys the executable graphs.
 hipError_t drop_graphs(lbm_ctx* c) {
@@ -217,9 +250,8 @@ hipError_t drop_graphs(lbm_ctx* c) {
   return e;
 }
 
-// Captures graph_steps alternating steps starting from grid `parity` (an
-// even count, so the replay ends on the grid it started from).  Only kernel
-// launches are recorded.
+// Captures graph_steps steps starting from grid `parity` and records which
+// grid a replay ends on (graph_end).  Only kernel launches are recorded.
 lbm_status build_graph(lbm_ctx* c, int parity) {
   hipError_t e = hipSuccess;
   if (!c->capture_stream) {
@@ -228,12 +260,10 @@ lbm_status build_graph(lbm_ctx* c, int parity) {
   }
   e = hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return hip_fail(e, "begin capture");
-  lbm_status st = LBM_OK;
   int cur = parity;
-  for (int32_t k = 0; k < c->graph_steps && st == LBM_OK; ++k) {
-    st = launch_steps_on(c, c->grid[cur], c->grid[cur ^ 1], c->capture_stream);
-    cur ^= 1;
-  }
+  int32_t done = 0;
+  lbm_status st = enqueue_steps(c, c->graph_steps, &cur, c->capture_stream, &done);
+  c->graph_end[parity] = cur;
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(c->capture_stream, &g);
   if (st != LBM_OK) {
@@ -368,19 +398,19 @@ lbm_status lbm_step(lbm_ctx* c, int32_t n) {
     replay = true;
     n -= c->graph_steps;
     c->t += c->graph_steps;
+    c->cur = c->graph_end[c->cur];
   }
   if (replay) {
     hipError_t e = hipEventRecord(c->replay_done, c->stream);
     if (e != hipSuccess) return hip_fail(e, "replay event");
     c->replayed = true;
   }
-  for (int32_t k = 0; k < n; ++k) {
-    st = launch_steps(c, c->grid[c->cur], c->grid[c->cur ^ 1]);
-    if (st != LBM_OK) return st;
-    c->cur ^= 1;
-    c->t += 1;
-  }
-  return LBM_OK;
+  int cur = c->cur;
+  int32_t done = 0;
+  st = enqueue_steps(c, n, &cur, c->stream, &done);
+  c->t += done;  // the steps enqueued before a failed launch still count
+  c->cur = cur;
+  return st;
 }
 
 lbm_status lbm_step_from(lbm_ctx* c, const void* src, void* dst) {

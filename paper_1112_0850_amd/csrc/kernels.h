@@ -23,6 +23,14 @@ struct Geo {
   int32_t yb;       // step kernel: rows are visited in bands of yb rows of y, z fastest
 };
 
+// Launch geometry of the two-step kernel: 64 x TY tiles in (x, y), z chunks.
+struct Geo2 {
+  int32_t nx, ny, nz;
+  int32_t xs;      // x stride of a population row, in cells
+  uint32_t plane;  // elements from one direction array to the next
+  int32_t ntx, nty, zc, nblocks, nb8;
+};
+
 constexpr int kBlock = 256;
 constexpr int kReduceBlocks = 1024;
 
@@ -45,6 +53,10 @@ hipError_t launch_mark_solids(int storage, const Geo& g, const PhysParams& ph, v
                               const uint8_t* flags, hipStream_t s);
 hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
                        const void* src, void* dst, const uint8_t* flags, hipStream_t s);
+// Two fused steps src = f*(t) -> dst = f*(t+2) (bit-identical to two launch_step calls;
+// not for the split design).
+hipError_t launch_step2(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
+                        const void* src, void* dst, const uint8_t* flags, hipStream_t s);
 hipError_t launch_obstacle(int storage, const Geo& g, const PhysParams& ph, void* grid,
                            const uint8_t* flags, hipStream_t s);
 hipError_t launch_macro(int storage, bool out_f64, const Geo& g, const PhysParams& ph,

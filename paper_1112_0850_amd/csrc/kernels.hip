@@ -564,6 +564,212 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
   }
 }
 
+// ---------------------------------------------------------------------------
+// Two fused steps per pass (temporal blocking over z): f*(t) -> f*(t+2).
+//
+// A block owns an output tile of 64 x TY cells in (x, y) and walks a chunk
+// of z planes.  Step 1 computes the intermediate level f*(t+1) on the tile
+// and its one-cell halo ((64 + 2) x (TY + 2) cells) of plane p, pulling from
+// src exactly as the single-step kernel does; step 2 computes f*(t+2) on the
+// tile at plane p - 1 from the intermediate level, which never leaves the
+// chip.  The 16 populations that move in x or y go through a ring of LDS
+// plane-arrays over the halo-extended tile, each value stored at the cell
+// that pulls it (A_i[x + c_i] = f*_i(x)): a step-2 read of direction i is
+// A_i at the cell's own index, and the own cell's value of direction j,
+// which a bounce-back needs, is A_j[x + c_j].  The three populations that do
+// not move in x or y (0 and the pure-z pair) stay in the registers of the
+// thread that owns the column.  The ring holds as many planes of a direction
+// as they are read: c_z = +1 two planes later (3 slots), c_z = 0 and c_z =
+// -1 up to one plane later (2 slots); two barriers per plane separate writes
+// from reads.  The next plane's 19 pulls are issued before the first barrier,
+// so their latency hides behind step 2.  Both steps run the single-step
+// kernel's pull, marker test, collision and rounding, and the intermediate
+// values are rounded to the storage type, so a pass equals two single steps
+// bit for bit.  Threads: TY + 2 waves, one per extended row (lane = x), plus
+// one wave for the 2 (TY + 2) halo cells left and right of the tile.  HBM
+// traffic per pass: one read of f*(t) (plus the halo lines that miss in L2)
+// and one write of f*(t+2) -- about half of two single steps.
+// ---------------------------------------------------------------------------
+constexpr int kTB2Arrays = 36;  // LDS plane-arrays of [TY + 2][66]
+constexpr int kTB2Chunk = 128;  // z planes per block
+
+// Tile rows per block.  Measured at 512^3: 4-byte storage runs best with 8
+// (11 waves of 150 VGPRs; 13 rows force the kernel under 128 VGPRs and it
+// spills), 2-byte storage with 13 (16 waves, 1024 threads); 8-byte storage
+// takes 4 so that its ring fits in LDS.
+template <typename T>
+__host__ __device__ constexpr int tb2_rows() {
+  return sizeof(T) >= 8 ? 4 : (sizeof(T) == 2 ? 13 : 8);
+}
+__host__ __device__ constexpr int tb2_nslot(int i) { return D3Q19::cz[i] > 0 ? 3 : 2; }
+// first plane-array of direction i (the 16 directions with c_x or c_y != 0)
+__host__ __device__ constexpr int tb2_base(int i) {
+  int b = 0;
+  for (int j = 1; j < i; ++j)
+    if (D3Q19::cx[j] != 0 || D3Q19::cy[j] != 0) b += tb2_nslot(j);
+  return b;
+}
+// plane-array of direction i holding plane p (p may be negative)
+__device__ __forceinline__ int tb2_slot(int i, int p) {
+  const int ns = tb2_nslot(i);
+  const int r = p % ns;
+  return tb2_base(i) + (r < 0 ? r + ns : r);
+}
+
+__device__ __forceinline__ int wrap_mod(int v, int n) {
+  const int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+template <int K, int WALLS, bool FORCE, bool INC>
+__global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void k_step2(
+    const typename Storage<K>::T* __restrict__ src, typename Storage<K>::T* __restrict__ dst,
+    const uint8_t* __restrict__ flags, Geo2 g, StepK<typename Storage<K>::C> k) {
+  using C = typename Storage<K>::C;
+  using T = typename Storage<K>::T;
+  constexpr int TY = tb2_rows<T>(), TX = 64, EX = TX + 2, EY = TY + 2;
+  constexpr bool SOLIDS = WALLS >= 1;
+  constexpr bool MARKERS = WALLS >= 1;
+  __shared__ T ring[kTB2Arrays * EY * EX];
+  // block -> tile: x tiles fastest, then y tiles, then z chunks; XCD k gets
+  // the k-th contiguous eighth of that order
+  const int b = blockIdx.x;
+  const int lb = (b < g.nb8) ? ((b & 7) * (g.nb8 >> 3) + (b >> 3)) : b;
+  const int x0 = (lb % g.ntx) * TX;
+  const int y0 = ((lb / g.ntx) % g.nty) * TY;
+  const int z0 = (lb / (g.ntx * g.nty)) * g.zc;
+  const int zend = min(z0 + g.zc, g.nz);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = int(threadIdx.x & 63);
+  // this thread's step-1 cell (ex, ey), tile coordinates; ex in [-1, 64], ey in [-1, TY]
+  int ex = lane, ey = wave - 1;
+  if (wave == TY + 2) {  // the halo columns x0 - 1 and x0 + 64 of every extended row
+    ey = lane < 2 * EY ? (lane >> 1) - 1 : TY;  // lanes past the halo repeat a halo cell
+    ex = (lane & 1) ? TX : -1;
+  }
+  const int gx = wrap_mod(x0 + ex, g.nx), gy = wrap_mod(y0 + ey, g.ny);
+  const bool interior = wave >= 1 && wave <= TY;  // also computes step 2 at (ex, ey)
+  const bool out_ok = interior && x0 + ex < g.nx && y0 + ey < g.ny;
+  // pull sources x - c_x and y - c_y at index c + 1 ({x + 1, x, x - 1}), periodic
+  const uint32_t xs_[3] = {uint32_t(gx + 1 == g.nx ? 0 : gx + 1), uint32_t(gx),
+                           uint32_t(gx == 0 ? g.nx - 1 : gx - 1)};
+  const int ys_[3] = {gy + 1 == g.ny ? 0 : gy + 1, gy, gy == 0 ? g.ny - 1 : gy - 1};
+  const size_t pb = size_t(g.plane) * sizeof(T);
+  auto ridx = [&](int i, int p, int ty, int tx) {
+    return (tb2_slot(i, p) * EY + (ty + 1)) * EX + (tx + 1);
+  };
+  // the next plane's pulls and flag byte, issued one iteration ahead
+  T nv[Q];
+  uint8_t nfl = 0;
+  auto issue = [&](int p) {
+    const int pz = wrap_mod(p, g.nz);
+    const int zs_[3] = {pz + 1 == g.nz ? 0 : pz + 1, pz, pz == 0 ? g.nz - 1 : pz - 1};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const uint32_t row = uint32_t(zs_[1 + D3Q19::cz[i]] * g.ny + ys_[1 + D3Q19::cy[i]]) *
+                           uint32_t(g.xs);
+      nv[i] = *elem_rx(src, pb, i, row, xs_[1 + D3Q19::cx[i]]);
+    }
+    nfl = SOLIDS ? flags[(size_t(pz) * g.ny + gy) * g.nx + gx] : uint8_t(0);
+  };
+  // own column's step-1 results: planes p - 1 (prev) and p - 2 (pp5)
+  T prev0 = T(0), prev5 = T(0), prev6 = T(0), pp5 = T(0);
+  uint8_t fl_prev = 0;
+  issue(z0 - 1);
+  for (int p = z0 - 1; p <= zend; ++p) {
+    // ---- step 1 at (gx, gy, p): the single-step kernel's update ----
+    const int pz = wrap_mod(p, g.nz);
+    const uint32_t own = uint32_t(pz * g.ny + gy) * uint32_t(g.xs) + uint32_t(gx);
+    const uint8_t fl = nfl;
+    const bool solid = SOLIDS && (fl & FLAG_SOLID);
+    C f[Q];
+    bool mark[Q], mov[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      mark[i] = MARKERS && i != 0 && is_marker<K, WALLS>(raw_bits<K>(nv[i]));
+      mov[i] = WALLS == 2 && i != 0 && raw_bits<K>(nv[i]) == Storage<K>::kMoving;
+      f[i] = C(nv[i]);
+    }
+    if (MARKERS) {
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        if (mark[i] && !solid) {
+          C bb = C(*elem(src, pb, D3Q19::opp[i], own));
+          if (WALLS == 2 && mov[i]) bb += k.Kw[i];
+          f[i] = bb;
+        }
+    }
+    if (FORCE && SOLIDS)
+      collide<C, FORCE, K == ST_F16, INC, K == ST_F32>(f, k, (fl & FLAG_NOFORCE) ? C(0) : C(1));
+    else
+      collide<C, FORCE, K == ST_F16, INC, K == ST_F32>(f, k, C(1));
+    const T marker = solid_marker<K>(fl, WALLS == 2);
+    T cur0, cur5, cur6;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      C o = f[i];
+      if constexpr (K == ST_F16) o = fp32_result(o);
+      const T v = solid ? marker : T(o);
+      if (i == 0) cur0 = v;
+      else if (i == 5) cur5 = v;
+      else if (i == 6) cur6 = v;
+      else {
+        const int tx = ex + D3Q19::cx[i], ty = ey + D3Q19::cy[i];
+        if (tx >= -1 && tx <= TX && ty >= -1 && ty <= TY) ring[ridx(i, p, ty, tx)] = v;
+      }
+    }
+    if (p < zend) issue(p + 1);
+    __syncthreads();
+    // ---- step 2 at (gx, gy, q = p - 1) from the intermediate level ----
+    const int q = p - 1;
+    if (interior && q >= z0) {
+      const int qz = wrap_mod(q, g.nz);
+      const uint32_t qown = uint32_t(qz * g.ny + gy) * uint32_t(g.xs) + uint32_t(gx);
+      const bool solid2 = SOLIDS && (fl_prev & FLAG_SOLID);
+      C h[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        T w;
+        if (i == 0) w = prev0;
+        else if (i == 5) w = pp5;
+        else if (i == 6) w = cur6;
+        else w = ring[ridx(i, q - D3Q19::cz[i], ey, ex)];
+        h[i] = C(w);
+        if (MARKERS && i != 0 && is_marker<K, WALLS>(raw_bits<K>(w)) && !solid2) {
+          // half-way bounce-back: the own cell's opposite population at plane q
+          const int j = D3Q19::opp[i];
+          T bt;
+          if (j == 5) bt = prev5;
+          else if (j == 6) bt = prev6;
+          else bt = ring[ridx(j, q, ey + D3Q19::cy[j], ex + D3Q19::cx[j])];
+          C bb = C(bt);
+          if (WALLS == 2 && raw_bits<K>(w) == Storage<K>::kMoving) bb += k.Kw[i];
+          h[i] = bb;
+        }
+      }
+      if (FORCE && SOLIDS)
+        collide<C, FORCE, K == ST_F16, INC, K == ST_F32>(h, k, (fl_prev & FLAG_NOFORCE) ? C(0) : C(1));
+      else
+        collide<C, FORCE, K == ST_F16, INC, K == ST_F32>(h, k, C(1));
+      const T marker2 = solid_marker<K>(fl_prev, WALLS == 2);
+      if (out_ok) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          C o = h[i];
+          if constexpr (K == ST_F16) o = fp32_result(o);
+          stream_store(elem(dst, pb, i, qown), solid2 ? marker2 : T(o));
+        }
+      }
+    }
+    __syncthreads();
+    pp5 = prev5;
+    prev0 = cur0;
+    prev5 = cur5;
+    prev6 = cur6;
+    fl_prev = fl;
+  }
+}
+
 // The separate obstacle kernel of the split design (WALLS = 3 steps): every
 // solid cell s writes, into its slot i, the value the fluid neighbour
 // x = s + c_i will pull along c_i: f*_opp(i)(x), plus the moving-wall term
@@ -1231,6 +1437,70 @@ hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const
     case ST_BF16: step_k<ST_BF16>(solids, force, g, ph, src, dst, flags, s); break;
     case ST_F64: step_k<ST_F64>(solids, force, g, ph, src, dst, flags, s); break;
     case ST_F32X: step_k<ST_F32X>(solids, force, g, ph, src, dst, flags, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Geometry of the two-step kernel's launch.
+static Geo2 make_geo2(const Geo& g, int rows) {
+  Geo2 h;
+  h.nx = g.nx;
+  h.ny = g.ny;
+  h.nz = g.nz;
+  h.xs = g.xs;
+  h.plane = g.plane;
+  h.ntx = (g.nx + 63) / 64;
+  h.nty = (g.ny + rows - 1) / rows;
+  h.zc = g.nz < kTB2Chunk ? g.nz : kTB2Chunk;
+  const int nzc = (g.nz + h.zc - 1) / h.zc;
+  h.nblocks = h.ntx * h.nty * nzc;
+  h.nb8 = (h.nblocks / 8) * 8;
+  return h;
+}
+
+template <int K, int WALLS, bool FORCE, bool INC>
+static void step2_t(const Geo& g, const PhysParams& ph, const void* src, void* dst,
+                    const uint8_t* flags, hipStream_t s) {
+  using S = Storage<K>;
+  constexpr int rows = tb2_rows<typename S::T>();
+  const Geo2 h = make_geo2(g, rows);
+  hipLaunchKernelGGL((k_step2<K, WALLS, FORCE, INC>), dim3(h.nblocks), dim3(64 * (rows + 3)), 0,
+                     s, reinterpret_cast<const typename S::T*>(src),
+                     reinterpret_cast<typename S::T*>(dst), flags, h,
+                     make_stepk<typename S::C>(ph));
+}
+
+template <int K, int WALLS, bool INC>
+static void step2_f(bool force, const Geo& g, const PhysParams& ph, const void* src, void* dst,
+                    const uint8_t* flags, hipStream_t s) {
+  if (force) step2_t<K, WALLS, true, INC>(g, ph, src, dst, flags, s);
+  else step2_t<K, WALLS, false, INC>(g, ph, src, dst, flags, s);
+}
+
+template <int K, bool INC>
+static void step2_w(bool solids, bool force, const Geo& g, const PhysParams& ph, const void* src,
+                    void* dst, const uint8_t* flags, hipStream_t s) {
+  if (!solids) step2_f<K, 0, INC>(force, g, ph, src, dst, flags, s);
+  else if (!ph.moving) step2_f<K, 1, INC>(force, g, ph, src, dst, flags, s);
+  else step2_f<K, 2, INC>(force, g, ph, src, dst, flags, s);
+}
+
+template <int K>
+static void step2_k(bool solids, bool force, const Geo& g, const PhysParams& ph, const void* src,
+                    void* dst, const uint8_t* flags, hipStream_t s) {
+  if (ph.incomp) step2_w<K, true>(solids, force, g, ph, src, dst, flags, s);
+  else step2_w<K, false>(solids, force, g, ph, src, dst, flags, s);
+}
+
+hipError_t launch_step2(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
+                        const void* src, void* dst, const uint8_t* flags, hipStream_t s) {
+  switch (storage) {
+    case ST_F32: step2_k<ST_F32>(solids, force, g, ph, src, dst, flags, s); break;
+    case ST_F16: step2_k<ST_F16>(solids, force, g, ph, src, dst, flags, s); break;
+    case ST_BF16: step2_k<ST_BF16>(solids, force, g, ph, src, dst, flags, s); break;
+    case ST_F64: step2_k<ST_F64>(solids, force, g, ph, src, dst, flags, s); break;
+    case ST_F32X: step2_k<ST_F32X>(solids, force, g, ph, src, dst, flags, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -47,11 +47,13 @@ class LBM:
     velocity of the cells flagged solid + moving (bit 2); ``equilibrium``:
     'qian' (u = j/rho) or 'incompressible' (He-Luo, u = j/rho0);
     ``obstacle_kernel=1`` selects the split design (a separate bounce-back
-    kernel before each step) instead of the fused solid markers."""
+    kernel before each step) instead of the fused solid markers;
+    ``steps_per_pass=2`` runs pairs of steps as one temporally blocked pass
+    (same results, bit for bit)."""
 
     def __init__(self, shape, tau, force=(0.0, 0.0, 0.0), storage="f32", flags=None, u0=None,
                  rho0=None, f16_scale_log2=0, x_align=0, device="cuda", wall_u=(0.0, 0.0, 0.0),
-                 equilibrium="qian", obstacle_kernel=0):
+                 equilibrium="qian", obstacle_kernel=0, steps_per_pass=0):
         self.shape = tuple(int(s) for s in shape)
         if len(self.shape) != 3:
             raise ValueError("shape must be (nz, ny, nx)")
@@ -68,7 +70,7 @@ class LBM:
         self.equilibrium = EQUILIBRIUM[equilibrium] if isinstance(equilibrium, str) \
             else int(equilibrium)
         self.params = A.params(self.shape, tau, self.force, self.storage, f16_scale_log2, x_align,
-                               self.wall_u, self.equilibrium, obstacle_kernel)
+                               self.wall_u, self.equilibrium, obstacle_kernel, steps_per_pass)
         xs, ds, gb, sb, ab = A.lbm_query(self.params)
         self.x_stride, self.dir_stride = xs, ds
         self.grid_bytes, self.adj_partials_bytes = gb, ab

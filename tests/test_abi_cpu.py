@@ -103,9 +103,11 @@ def test_invalid_params_rejected(kw, msg):
 
 
 def test_params_layout_and_obstacle_field():
-    # six int32, tau, force[3], wall_u[3], equilibrium, obstacle_kernel: 88 bytes, no padding
-    assert ctypes.sizeof(A.lbm_params) == 88
+    # six int32, tau, force[3], wall_u[3], equilibrium, obstacle_kernel, steps_per_pass:
+    # 92 bytes padded to 96 (the library checks the same layout at compile time)
+    assert ctypes.sizeof(A.lbm_params) == 96
     assert A.lbm_params.wall_u.offset == 56 and A.lbm_params.equilibrium.offset == 80
+    assert A.lbm_params.steps_per_pass.offset == 88
     p = A.params((4, 4, 4), 0.6, wall_u=(0.1, 0, 0), equilibrium=A.LBM_EQ_INCOMPRESSIBLE)
     A.lbm_query(p)
     p.obstacle_kernel = 1
@@ -197,3 +199,14 @@ def test_copy_probe_argument_errors():
             A.lbm_copy_probe(*args, None)
         assert e.value.status == A.LBM_E_ARG
     A.lbm_copy_probe(c, a, 0, 4, 1, 0, None)  # nothing to copy: no launch
+
+
+def test_steps_per_pass_option():
+    for v in (0, 1, 2):
+        A.lbm_query(A.params((4, 4, 4), 0.6, steps_per_pass=v))
+    with pytest.raises(A.LBMError) as e:
+        A.lbm_query(A.params((4, 4, 4), 0.6, steps_per_pass=3))
+    assert e.value.status == A.LBM_E_ARG and "steps_per_pass" in str(e.value)
+    with pytest.raises(A.LBMError) as e:
+        A.lbm_query(A.params((4, 4, 4), 0.6, steps_per_pass=2, obstacle_kernel=1))
+    assert e.value.status == A.LBM_E_UNSUPPORTED

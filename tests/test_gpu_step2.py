@@ -1,0 +1,162 @@
+"""The two-step pass (steps_per_pass = 2: pairs of steps fused into one
+temporally blocked kernel that keeps the intermediate level on chip) gives
+the same bits as single steps -- every storage, resting and moving walls,
+no-force cells, both equilibria, ragged and degenerate shapes, several z
+chunks, the unpadded layout, graph replays, odd step counts -- and the
+oracle's result within the FP32 bar; at the benchmark's full size as well."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_1112_0850_amd import inputs as I
+from paper_1112_0850_amd.lbm import LBM
+from tests.gpu_util import check_solids, rel_linf, say
+
+pytestmark = pytest.mark.gpu
+
+STORAGES = ["f32", "f16", "bf16", "f64", "f32x"]
+
+
+def _pair(shape, tau, F, storage, n, **kw):
+    s = 10 if storage == "f16" else 0
+    one = LBM(shape, tau, F, storage, f16_scale_log2=s, **kw).step(n)
+    two = LBM(shape, tau, F, storage, f16_scale_log2=s, steps_per_pass=2, **kw).step(n)
+    torch.cuda.synchronize()
+    return one, two
+
+
+def _same(one, two):
+    """Equal bytes in the current grids; on a difference, report where."""
+    assert one.t == two.t
+    a, b = one.grids[one.current], two.grids[two.current]
+    if torch.equal(a, b):
+        return True
+    nz, ny, nx = one.shape
+    va, vb = one.populations()[..., :nx], two.populations()[..., :nx]
+    ia = va.contiguous().view(torch.int16 if va.element_size() == 2 else
+                              (torch.int32 if va.element_size() == 4 else torch.int64))
+    ib = vb.contiguous().view(ia.dtype)
+    d = (ia != ib).nonzero().cpu().numpy()
+    say(f"  {len(d)} differing elements; first (i, z, y, x): {d[:8].tolist()}")
+    say(f"  per direction: {np.bincount(d[:, 0], minlength=19).tolist()}")
+    return False
+
+
+def _u0(shape, seed, amp=0.03):
+    rng = np.random.default_rng(seed)
+    return torch.from_numpy(amp * (rng.random((3,) + shape) - 0.5)).float()
+
+
+CASES = {
+    # name: (shape, kwargs)
+    "ragged_porous": ((7, 11, 100), "flags"),
+    "periodic": ((9, 16, 128), None),
+    "moving_walls": ((10, 12, 70), "moving"),
+    "z_chunks": ((300, 9, 70), "flags"),
+    "single_cell": ((1, 1, 1), None),
+    "thin_slab": ((1, 5, 1), None),
+    "narrow": ((3, 2, 17), "flags"),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("storage", STORAGES)
+def test_two_step_pass_is_bit_identical(storage, case):
+    shape, geo = CASES[case]
+    say("two-step pass vs single steps", storage, case, shape)
+    kw = dict(u0=_u0(shape, 3))
+    if geo == "flags":
+        kw["flags"] = I.random_flags(shape, 9, solid_fraction=0.2, noforce_fraction=0.15)
+    elif geo == "moving":
+        fl = I.random_flags(shape, 10, solid_fraction=0.15, noforce_fraction=0.1) | I.cavity_flags(shape)
+        kw.update(flags=fl, wall_u=(0.04, -0.01, 0.02))
+    if "flags" in kw:
+        kw["u0"][:, torch.from_numpy(kw["flags"] & 1 == 1)] = 0
+    for eq in ("qian", "incompressible"):
+        one, two = _pair(shape, 0.63, (2e-5, -1e-5, 3e-5), storage, 9, equilibrium=eq, **kw)
+        assert _same(one, two), eq
+        if "flags" in kw:
+            check_solids(two, kw["flags"])
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_two_step_pass_unpadded_and_without_force(storage):
+    shape = (6, 10, 65)
+    say("two-step pass, unpadded rows, no force", storage)
+    fl = I.random_flags(shape, 4, solid_fraction=0.2)
+    one, two = _pair(shape, 0.7, (0, 0, 0), storage, 8, flags=fl, x_align=1, u0=_u0(shape, 5))
+    assert two.x_stride == 65 and _same(one, two)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_two_step_pass_with_graph_replays(storage):
+    """Graphs of 6 steps (three fused passes: the replay ends on the other
+    grid) interleaved with odd eager counts."""
+    shape = (8, 9, 70)
+    say("two-step pass under graph replays", storage)
+    fl = I.random_flags(shape, 6, solid_fraction=0.2, noforce_fraction=0.1)
+    s = 10 if storage == "f16" else 0
+    ref = LBM(shape, 0.6, (1e-5, 0, 0), storage, flags=fl, u0=_u0(shape, 7), f16_scale_log2=s)
+    g = LBM(shape, 0.6, (1e-5, 0, 0), storage, flags=fl, u0=_u0(shape, 7), f16_scale_log2=s,
+            steps_per_pass=2).use_graphs(6)
+    for n in (6, 3, 12, 1, 6, 5):
+        ref.step(n)
+        g.step(n)
+        torch.cuda.synchronize()
+        assert _same(ref, g), n
+
+
+def test_two_step_pass_porous_parity_vs_oracle():
+    """The porous parity case run in pairs: FP32 within 1e-5 of the FP64
+    oracle after 100 steps."""
+    shape = (64, 64, 64)
+    say("two-step pass, porous 64^3 vs oracle")
+    flags = I.sphere_pack(shape, 0.10, seed=12345)
+    u0 = I.smooth_field(64, 99, amplitude=0.02, modes=4)
+    u0[:, flags & 1 == 1] = 0
+    u0 = u0.astype(np.float32).astype(np.float64)
+    sim = LBM(shape, 0.55, (1e-6, 0, 0), "f32", flags=flags, u0=torch.from_numpy(u0).float(),
+              steps_per_pass=2).step(100)
+    f = O.step(O.init(shape, flags, None, u0), 0.55, (1e-6, 0, 0), flags, n=100)
+    rho, u = sim.macroscopics(f64=True)
+    rho_r, u_r = O.macroscopics(f, (1e-6, 0, 0), flags)
+    fl = (flags & 1) == 0
+    e_rho, e_u = rel_linf(rho.cpu().numpy(), rho_r, fl), rel_linf(u.cpu().numpy(), u_r, fl)
+    say(f"  rel L-inf rho {e_rho:.2e}  u {e_u:.2e}")
+    assert e_rho <= 1e-5 and e_u <= 1e-5
+
+
+@pytest.mark.parametrize("storage,s", [("f32", 0), ("f16", 12)])
+def test_two_step_pass_at_full_size(storage, s):
+    """The benchmark's 512^3 porous box (10% spheres, seed 12345, tau 0.55,
+    g_x 1e-6) from a sheared start: 6 steps in fused pairs == 6 single steps,
+    every byte of the grid."""
+    n = 512
+    say(f"two-step pass at {n}^3 porous, {storage}")
+    flags = I.sphere_pack((n, n, n), 0.10, seed=12345)
+    u0 = I.shear_waves((n, n, n), seed=21, amplitude=0.02)
+    u0[:, flags & 1 == 1] = 0
+    u0 = torch.from_numpy(u0)
+    one = LBM((n, n, n), 0.55, (1e-6, 0, 0), storage, flags=flags, u0=u0, f16_scale_log2=s).step(6)
+    two = LBM((n, n, n), 0.55, (1e-6, 0, 0), storage, flags=flags, u0=u0, f16_scale_log2=s,
+              steps_per_pass=2).step(6)
+    torch.cuda.synchronize()
+    assert _same(one, two)
+    del one, two
+    torch.cuda.empty_cache()
+
+
+def test_two_step_pass_cavity_at_full_size():
+    n = 512
+    say(f"two-step pass at {n}^3 lid-driven cavity, f32")
+    flags = I.cavity_flags((n, n, n))
+    kw = dict(flags=flags, wall_u=(0.05, 0, 0))
+    one = LBM((n, n, n), 0.55, (0, 0, 0), "f32", **kw).step(4)
+    two = LBM((n, n, n), 0.55, (0, 0, 0), "f32", steps_per_pass=2, **kw).step(4)
+    torch.cuda.synchronize()
+    assert _same(one, two)
+    del one, two
+    torch.cuda.empty_cache()
