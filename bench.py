@@ -569,6 +569,8 @@ def profile_summary(trace_dir, fetch_dir, write_dir, n=512):
              "|---|---|---|---|---|---|---|---|---|"]
     record = {}
     for (name, grid), v in sorted(times.items(), key=lambda kv: -sum(kv[1])):
+        if name.startswith("void lbm::k_copy_v"):
+            continue  # the copy sweep's variants: reported on the bench line
         avg_us = float(np.mean(v))
         box = box_of(name, grid) if name.startswith("void lbm::k_") else None
         row = [name.replace("void ", "")[:44], f"{box}^3" if box else "", str(len(v)), f"{avg_us:.1f}"]
@@ -621,7 +623,7 @@ def trace_summary(trace_dir, bench_json):
     out = ["| kernel | box | calls | avg us | min us | max us | share of GPU time |",
            "|---|---|---|---|---|---|---|"]
     for (name, grid), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
-        if sum(v) / total < 0.002:
+        if sum(v) / total < 0.002 or name.startswith("void lbm::k_copy_v"):
             continue
         box = box_of(name, grid) if name.startswith("void lbm::k_") else None
         out.append(f"| {name.replace('void ', '')} | {f'{box}^3' if box else ''} | {len(v)} | "
