@@ -593,13 +593,15 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 constexpr int kTB2Arrays = 36;  // LDS plane-arrays of [TY + 2][66]
 constexpr int kTB2Chunk = 128;  // z planes per block
 
-// Tile rows per block.  Measured at 512^3: 4-byte storage runs best with 8
-// (11 waves of 150 VGPRs; 13 rows force the kernel under 128 VGPRs and it
-// spills), 2-byte storage with 13 (16 waves, 1024 threads); 8-byte storage
-// takes 4 so that its ring fits in LDS.
+// Tile rows per block.  With the pulls addressed as one wave-uniform base
+// plus 32-bit offsets the kernel fits 128 VGPRs (114 for 4-byte, 88 for
+// 2-byte storage) without spills, so 13 rows (16 waves, 1024 threads) fit;
+// measured at 512^3 with 4-byte storage 13 rows beat 8 by 13%, 2-byte
+// storage runs the same with either.  8-byte storage takes 4 so that its
+// ring fits in LDS.
 template <typename T>
 __host__ __device__ constexpr int tb2_rows() {
-  return sizeof(T) >= 8 ? 4 : (sizeof(T) == 2 ? 13 : 8);
+  return sizeof(T) >= 8 ? 4 : 13;
 }
 __host__ __device__ constexpr int tb2_nslot(int i) { return D3Q19::cz[i] > 0 ? 3 : 2; }
 // first plane-array of direction i (the 16 directions with c_x or c_y != 0)
@@ -661,6 +663,9 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
   // the next plane's pulls and flag byte, issued one iteration ahead
   T nv[Q];
   uint8_t nfl = 0;
+  // Each pull is a scalar base (direction array) plus a 32-bit per-lane
+  // element offset (row + x), which keeps 64-bit address arithmetic out of
+  // the vector registers.
   auto issue = [&](int p) {
     const int pz = wrap_mod(p, g.nz);
     const int zs_[3] = {pz + 1 == g.nz ? 0 : pz + 1, pz, pz == 0 ? g.nz - 1 : pz - 1};
@@ -668,7 +673,7 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
     for (int i = 0; i < Q; ++i) {
       const uint32_t row = uint32_t(zs_[1 + D3Q19::cz[i]] * g.ny + ys_[1 + D3Q19::cy[i]]) *
                            uint32_t(g.xs);
-      nv[i] = *elem_rx(src, pb, i, row, xs_[1 + D3Q19::cx[i]]);
+      nv[i] = *elem(src, pb, i, row + xs_[1 + D3Q19::cx[i]]);
     }
     nfl = SOLIDS ? flags[(size_t(pz) * g.ny + gy) * g.nx + gx] : uint8_t(0);
   };
