@@ -623,6 +623,44 @@ __device__ __forceinline__ int wrap_mod(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
+// An opaque copy of a wave-uniform 64-bit value: an empty asm statement on a
+// scalar register pair, kept in place.  The two-step kernel walks the 19
+// direction arrays with a running base address renewed on every plane
+// through such copies; left to itself the compiler hoists all 19 source and
+// 19 destination bases out of the plane loop, they overflow the scalar
+// register file, and every use reloads them from spill lanes with vector
+// instructions.
+__device__ __forceinline__ uint64_t uniform_opaque(uint64_t v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+// An opaque copy of a per-lane 32-bit value: an LDS ring address is one such
+// base per plane phase plus a compile-time offset, which the LDS instruction
+// takes as its immediate.
+__device__ __forceinline__ uint32_t lane_opaque(uint32_t v) {
+  asm("" : "+v"(v));
+  return v;
+}
+// The same for a value used in several conditional blocks: a fresh copy in
+// each block keeps the compiler from sharing one 64-bit widened offset
+// between the blocks, which would rule out the scalar-base load form.
+__device__ __forceinline__ uint32_t lane_fresh(uint32_t v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+// Element at `base` (a wave-uniform global address) + `off` bytes (per
+// lane): the scalar-base + 32-bit-offset form of global loads and stores
+// (the pointer is made in the global address space, else the compiler can
+// only emit flat accesses with 64-bit per-lane addresses).
+template <typename T>
+__device__ __forceinline__ T load_at(uint64_t base, uint32_t off) {
+  return *reinterpret_cast<const __attribute__((address_space(1))) T*>(base + off);
+}
+template <typename T>
+__device__ __forceinline__ void store_nt_at(uint64_t base, uint32_t off, T v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<__attribute__((address_space(1))) T*>(base + off));
+}
+
 template <int K, int WALLS, bool FORCE, bool INC>
 __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void k_step2(
     const typename Storage<K>::T* __restrict__ src, typename Storage<K>::T* __restrict__ dst,
@@ -630,6 +668,8 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
   using C = typename Storage<K>::C;
   using T = typename Storage<K>::T;
   constexpr int TY = tb2_rows<T>(), TX = 64, EX = TX + 2, EY = TY + 2;
+  constexpr uint32_t SZ = sizeof(T);
+  constexpr uint32_t PLB = uint32_t(EY * EX) * SZ;  // bytes of one LDS plane-array
   constexpr bool SOLIDS = WALLS >= 1;
   constexpr bool MARKERS = WALLS >= 1;
   __shared__ T ring[kTB2Arrays * EY * EX];
@@ -652,30 +692,45 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
   const int gx = wrap_mod(x0 + ex, g.nx), gy = wrap_mod(y0 + ey, g.ny);
   const bool interior = wave >= 1 && wave <= TY;  // also computes step 2 at (ex, ey)
   const bool out_ok = interior && x0 + ex < g.nx && y0 + ey < g.ny;
-  // pull sources x - c_x and y - c_y at index c + 1 ({x + 1, x, x - 1}), periodic
-  const uint32_t xs_[3] = {uint32_t(gx + 1 == g.nx ? 0 : gx + 1), uint32_t(gx),
-                           uint32_t(gx == 0 ? g.nx - 1 : gx - 1)};
-  const int ys_[3] = {gy + 1 == g.ny ? 0 : gy + 1, gy, gy == 0 ? g.ny - 1 : gy - 1};
-  const size_t pb = size_t(g.plane) * sizeof(T);
-  auto ridx = [&](int i, int p, int ty, int tx) {
-    return (tb2_slot(i, p) * EY + (ty + 1)) * EX + (tx + 1);
+  // Byte offsets inside one direction array (< 4 GiB, checked on the host):
+  // pull columns x - c_x and rows y - c_y at index c + 1 ({x + 1, x, x - 1}),
+  // periodic, and the stride of one z plane.
+  const uint32_t rowb = uint32_t(g.xs) * SZ;
+  const uint32_t xb_[3] = {uint32_t(gx + 1 == g.nx ? 0 : gx + 1) * SZ, uint32_t(gx) * SZ,
+                           uint32_t(gx == 0 ? g.nx - 1 : gx - 1) * SZ};
+  const uint32_t yb_[3] = {uint32_t(gy + 1 == g.ny ? 0 : gy + 1) * rowb, uint32_t(gy) * rowb,
+                           uint32_t(gy == 0 ? g.ny - 1 : gy - 1) * rowb};
+  const uint32_t zstride = uint32_t(g.ny) * rowb;
+  const uint32_t own_yx = yb_[1] + xb_[1];
+  const uint32_t fl_yx = uint32_t(gy) * uint32_t(g.nx) + uint32_t(gx);
+  const uint32_t fl_z = uint32_t(g.ny) * uint32_t(g.nx);
+  const uint64_t src_u = reinterpret_cast<uint64_t>(src), dst_u = reinterpret_cast<uint64_t>(dst);
+  const uint64_t pb = uint64_t(g.plane) * SZ;  // bytes from one direction array to the next
+  // LDS ring: this lane's cell of the extended tile in plane-array 0; the
+  // element of direction i in its array for plane phase m, (dy, dx) cells
+  // away, sits at lane_b + m PLB + [tb2_base(i) PLB + (dy EX + dx) SZ], the
+  // bracket a compile-time constant.
+  const uint32_t lane_b = uint32_t((ey + 1) * EX + ex + 1) * SZ;
+  auto ring_at = [&](uint32_t base, int i, int dy, int dx) -> T& {
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(ring) + base +
+                                 (uint32_t(tb2_base(i)) * PLB + uint32_t((dy * EX + dx) * int(SZ))));
   };
+  auto phase_base = [&](int p, int ns) { return lane_opaque(lane_b + uint32_t(wrap_mod(p, ns)) * PLB); };
   // the next plane's pulls and flag byte, issued one iteration ahead
   T nv[Q];
   uint8_t nfl = 0;
-  // Each pull is a scalar base (direction array) plus a 32-bit per-lane
-  // element offset (row + x), which keeps 64-bit address arithmetic out of
-  // the vector registers.
   auto issue = [&](int p) {
     const int pz = wrap_mod(p, g.nz);
-    const int zs_[3] = {pz + 1 == g.nz ? 0 : pz + 1, pz, pz == 0 ? g.nz - 1 : pz - 1};
+    const uint32_t zb_[3] = {uint32_t(pz + 1 == g.nz ? 0 : pz + 1) * zstride, uint32_t(pz) * zstride,
+                             uint32_t(pz == 0 ? g.nz - 1 : pz - 1) * zstride};
+    uint64_t base = uniform_opaque(src_u);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const uint32_t row = uint32_t(zs_[1 + D3Q19::cz[i]] * g.ny + ys_[1 + D3Q19::cy[i]]) *
-                           uint32_t(g.xs);
-      nv[i] = *elem(src, pb, i, row + xs_[1 + D3Q19::cx[i]]);
+      nv[i] = load_at<T>(base, zb_[1 + D3Q19::cz[i]] + yb_[1 + D3Q19::cy[i]] +
+                                   xb_[1 + D3Q19::cx[i]]);
+      if (i + 1 < Q) base = uniform_opaque(base + pb);
     }
-    nfl = SOLIDS ? flags[(size_t(pz) * g.ny + gy) * g.nx + gx] : uint8_t(0);
+    nfl = SOLIDS ? flags[uint32_t(pz) * fl_z + fl_yx] : uint8_t(0);
   };
   // own column's step-1 results: planes p - 1 (prev) and p - 2 (pp5)
   T prev0 = T(0), prev5 = T(0), prev6 = T(0), pp5 = T(0);
@@ -683,8 +738,7 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
   issue(z0 - 1);
   for (int p = z0 - 1; p <= zend; ++p) {
     // ---- step 1 at (gx, gy, p): the single-step kernel's update ----
-    const int pz = wrap_mod(p, g.nz);
-    const uint32_t own = uint32_t(pz * g.ny + gy) * uint32_t(g.xs) + uint32_t(gx);
+    const uint32_t ownb = uint32_t(wrap_mod(p, g.nz)) * zstride + own_yx;
     const uint8_t fl = nfl;
     const bool solid = SOLIDS && (fl & FLAG_SOLID);
     C f[Q];
@@ -696,19 +750,30 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
       f[i] = C(nv[i]);
     }
     if (MARKERS) {
+      // pairs (i, i + 1) = (c, -c): each bounces back the other's slot of the own cell
+      uint64_t base = uniform_opaque(src_u + pb);
 #pragma unroll
-      for (int i = 1; i < Q; ++i)
+      for (int i = 1; i < Q; i += 2) {
+        const uint64_t bo = base + pb;
         if (mark[i] && !solid) {
-          C bb = C(*elem(src, pb, D3Q19::opp[i], own));
+          C bb = C(load_at<T>(bo, lane_fresh(ownb)));
           if (WALLS == 2 && mov[i]) bb += k.Kw[i];
           f[i] = bb;
         }
+        if (mark[i + 1] && !solid) {
+          C bb = C(load_at<T>(base, lane_fresh(ownb)));
+          if (WALLS == 2 && mov[i + 1]) bb += k.Kw[i + 1];
+          f[i + 1] = bb;
+        }
+        if (i + 2 < Q) base = uniform_opaque(bo + pb);
+      }
     }
     if (FORCE && SOLIDS)
       collide<C, FORCE, K == ST_F16, INC, K == ST_F32>(f, k, (fl & FLAG_NOFORCE) ? C(0) : C(1));
     else
       collide<C, FORCE, K == ST_F16, INC, K == ST_F32>(f, k, C(1));
     const T marker = solid_marker<K>(fl, WALLS == 2);
+    const uint32_t w2 = phase_base(p, 2), w3 = phase_base(p, 3);
     T cur0, cur5, cur6;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -720,7 +785,8 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
       else if (i == 6) cur6 = v;
       else {
         const int tx = ex + D3Q19::cx[i], ty = ey + D3Q19::cy[i];
-        if (tx >= -1 && tx <= TX && ty >= -1 && ty <= TY) ring[ridx(i, p, ty, tx)] = v;
+        if (tx >= -1 && tx <= TX && ty >= -1 && ty <= TY)
+          ring_at(tb2_nslot(i) == 3 ? w3 : w2, i, D3Q19::cy[i], D3Q19::cx[i]) = v;
       }
     }
     if (p < zend) issue(p + 1);
@@ -728,9 +794,10 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
     // ---- step 2 at (gx, gy, q = p - 1) from the intermediate level ----
     const int q = p - 1;
     if (interior && q >= z0) {
-      const int qz = wrap_mod(q, g.nz);
-      const uint32_t qown = uint32_t(qz * g.ny + gy) * uint32_t(g.xs) + uint32_t(gx);
+      const uint32_t qownb = uint32_t(wrap_mod(q, g.nz)) * zstride + own_yx;
       const bool solid2 = SOLIDS && (fl_prev & FLAG_SOLID);
+      // plane q - c_z of direction i: p - 2 (c_z = +1, 3 slots), p - 1, p
+      const uint32_t r3 = phase_base(p - 2, 3), r2 = phase_base(q, 2), b3 = phase_base(q, 3);
       C h[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
@@ -738,7 +805,7 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
         if (i == 0) w = prev0;
         else if (i == 5) w = pp5;
         else if (i == 6) w = cur6;
-        else w = ring[ridx(i, q - D3Q19::cz[i], ey, ex)];
+        else w = ring_at(D3Q19::cz[i] > 0 ? r3 : (D3Q19::cz[i] == 0 ? r2 : w2), i, 0, 0);
         h[i] = C(w);
         if (MARKERS && i != 0 && is_marker<K, WALLS>(raw_bits<K>(w)) && !solid2) {
           // half-way bounce-back: the own cell's opposite population at plane q
@@ -746,7 +813,7 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
           T bt;
           if (j == 5) bt = prev5;
           else if (j == 6) bt = prev6;
-          else bt = ring[ridx(j, q, ey + D3Q19::cy[j], ex + D3Q19::cx[j])];
+          else bt = ring_at(tb2_nslot(j) == 3 ? b3 : r2, j, D3Q19::cy[j], D3Q19::cx[j]);
           C bb = C(bt);
           if (WALLS == 2 && raw_bits<K>(w) == Storage<K>::kMoving) bb += k.Kw[i];
           h[i] = bb;
@@ -758,11 +825,13 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
         collide<C, FORCE, K == ST_F16, INC, K == ST_F32>(h, k, C(1));
       const T marker2 = solid_marker<K>(fl_prev, WALLS == 2);
       if (out_ok) {
+        uint64_t base = uniform_opaque(dst_u);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           C o = h[i];
           if constexpr (K == ST_F16) o = fp32_result(o);
-          stream_store(elem(dst, pb, i, qown), solid2 ? marker2 : T(o));
+          store_nt_at<T>(base, qownb, solid2 ? marker2 : T(o));
+          if (i + 1 < Q) base = uniform_opaque(base + pb);
         }
       }
     }
