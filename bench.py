@@ -65,25 +65,42 @@ def parse():
     ap.add_argument("--profile-summary", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="summarise rocprofv3 CSV output (kernel trace, FETCH_SIZE and "
                          "WRITE_SIZE passes of this script) into profiles/ and exit")
+    ap.add_argument("--valu-summary", nargs=2, metavar=("TRACE_DIR", "COUNTER_DIR"),
+                    help="summarise a rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU "
+                         "SQ_BUSY_CYCLES GRBM_GUI_ACTIVE pass of this script (vector-instruction "
+                         "issue of the step kernels at the porous 512^3 box) as markdown and exit")
     return ap.parse_args()
 
 
 REPS = 5
 
 
-def timed_steps(sim, torch, steps, warmup, clocks=None, detail=None, reps=REPS):
+def rep_sizes(steps, reps, unit=1):
+    """Steps of each timed repetition: `steps` split into at most `reps`
+    near-equal parts that are multiples of `unit`, any remainder going to
+    the last part."""
+    units, rem = divmod(steps, unit)
+    reps = max(1, min(reps, units))
+    sizes = [unit * (units // reps + (1 if r < units % reps else 0)) for r in range(reps)]
+    sizes[-1] += rem
+    return sizes
+
+
+def timed_steps(sim, torch, steps, warmup, clocks=None, detail=None, reps=REPS, unit=1):
     """Milliseconds per fused step: `warmup` untimed steps, then exactly
     `steps` timed steps bracketed by device synchronisation, split into
     `reps` consecutive repetitions whose HIP events (recorded on the solver's
-    stream) give one per-step time each; returns their median.  With a dict
-    `detail`, also the minimum, maximum, every repetition and the plain
-    average over all `steps`.  With a dict `clocks`, a timer thread reads the
-    GPU clocks (sysfs) 0.5 s into the timed steps."""
+    stream) give one per-step time each; returns their median.  Each
+    repetition holds a multiple of `unit` steps (the steps one launch
+    performs), any remainder going to the last.  With a dict `detail`, also
+    the minimum, maximum, every repetition and the plain average over all
+    `steps`.  With a dict `clocks`, a timer thread reads the GPU clocks
+    (sysfs) 0.5 s into the timed steps."""
     import statistics
     sim.step(warmup)
     torch.cuda.synchronize()
-    reps = max(1, min(reps, steps))
-    sizes = [steps // reps + (1 if r < steps % reps else 0) for r in range(reps)]
+    sizes = rep_sizes(steps, reps, unit)
+    reps = len(sizes)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
     timer = None
     if clocks is not None:
@@ -132,7 +149,8 @@ def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s
     n = round(n_cells ** (1 / 3))
     sim = LBM((n, n, n), 0.55, (1e-6, 0.0, 0.0), storage, flags=flags_t, f16_scale_log2=s, **kw)
     rep = {}
-    ms = timed_steps(sim, torch, steps, warmup, clocks, detail=rep)
+    spl = kw.get("steps_per_pass") or 1
+    ms = timed_steps(sim, torch, steps, warmup, clocks, detail=rep, unit=spl)
     r = sim.reduce().cpu().numpy()
     if fields is not None:
         fields[storage] = sim.macroscopics(f64=True)
@@ -145,7 +163,7 @@ def forward_leg(torch, LBM, flags_t, n_cells, n_fluid, storage, steps, warmup, s
         "bytes_per_update": bpu, "alg_bytes_per_step": alg_bytes,
         "alg_gbs": alg_bytes / ms / 1e6, "hbm_frac": alg_bytes / ms / 1e6 / HBM_PEAK_GBS,
         "mass": float(r[0]), "finite": bool(all(math.isfinite(float(v)) for v in r)),
-        "timing": rep,
+        "timing": rep, "steps_per_launch": spl,
     }
     if storage == "f16":
         out["f16_scale_log2"] = s
@@ -479,15 +497,12 @@ def code_hash():
     return h.hexdigest()
 
 
-def traffic_entry(alg_bytes, ms):
-    """HBM traffic per launch from the committed rocprofv3 counter summary,
+def traffic_entry(key):
+    """HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated) per launch of the
+    kernel recorded under `key` in the committed rocprofv3 counter summary,
     or None when the kernel source changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    t = json.load(open(TRAFFIC_FILE))
-    if t.get("code_sha256") != code_hash():
-        return None
-    return t.get("traffic_bytes_per_launch")
+    rec = traffic_record(key)
+    return rec["fetch_bytes"] + rec["write_bytes"] if rec else None
 
 
 def traffic_record(key):
@@ -517,11 +532,11 @@ KERNELS = {  # record key -> (kernel name, box edge, bytes per fluid update, por
 def launch_threads(name, n):
     """Threads a launch of the named kernel has on an n^3 box (64 * M-cell
     segments per row, four per block, M = 4 for the 16-bit step kernels; the
-    two-step kernel: 64 x TY tiles (TY = 8, 13 for 16-bit, 4 for FP64) and
+    two-step kernel: 64 x TY tiles (TY = 13; 4 for FP64, 8 for F32X) and
     128-plane z chunks, 64 (TY + 3) threads per block)."""
     if name.startswith("void lbm::k_step2<"):
         k = int(name.split("<")[1].split(",")[0])
-        ty = {1: 13, 2: 13, 3: 4}.get(k, 8)
+        ty = {3: 4, 4: 8}.get(k, 13)
         return -(-n // 64) * -(-n // ty) * -(-n // min(n, 128)) * 64 * (ty + 3)
     m = 4 if name.startswith("void lbm::k_step<1,") or name.startswith("void lbm::k_step<2,") else 1
     nseg = -(-n // (64 * m))
@@ -605,6 +620,49 @@ def profile_summary(trace_dir, fetch_dir, write_dir, n=512):
     return 0
 
 
+def valu_summary(trace_dir, counter_dir, n=512, simds=1024, xcds=8):
+    """Vector-instruction issue of the step kernels at the n^3 box from a
+    VALU counter pass: wave-instructions per launch and per 64 cell updates,
+    and VALU busy = SQ_ACTIVE_INST_VALU (quad-cycles) x 4 / simds against the
+    kernel's own duration in cycles (GRBM_GUI_ACTIVE is summed over the
+    xcds); the launch time is the kernel trace's average for the same kernel
+    and box."""
+    import csv
+    import glob
+    import statistics
+    cnt = {}
+    for r in csv.DictReader(open(glob.glob(os.path.join(counter_dir, "*counter_collection.csv"))[0])):
+        name = r["Kernel_Name"].split("(")[0]
+        if not name.startswith("void lbm::k_step"):
+            continue
+        key = (name if name.startswith("void ") else name, int(r["Grid_Size"]))
+        cnt.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    times = {}
+    for r in csv.DictReader(open(glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0])):
+        key = (r["Kernel_Name"].split("(")[0], int(r["Grid_Size_X"]))
+        times.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = ["| kernel | steps per launch | VALU wave-instr. per launch | per 64 cell updates | "
+             "VALU busy | VALU issue per launch (ms) | launch (ms) |", "|---|---|---|---|---|---|---|"]
+    for (name, grid), c in sorted(cnt.items()):
+        if box_of(name, grid) != n or not all(k in c for k in ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU",
+                                                                "GRBM_GUI_ACTIVE")):
+            continue
+        spl = 2 if name.startswith("void lbm::k_step2<") else 1
+        insts = statistics.mean(c["SQ_INSTS_VALU"])
+        quad = statistics.mean(c["SQ_ACTIVE_INST_VALU"])
+        cycles = statistics.mean(c["GRBM_GUI_ACTIVE"]) / xcds
+        busy = quad * 4 / simds / cycles
+        launch = statistics.mean(times[(name, grid)]) / 1e3 if (name, grid) in times else None
+        issue = busy * launch if launch else None
+        lines.append(f"| {name.replace('void lbm::', '')} | {spl} | {insts:.4g} | "
+                     f"{insts / (n ** 3 / 64 * spl):.0f} | {100 * busy:.0f}% | "
+                     f"{issue:.2f} | {launch:.2f} |" if launch else
+                     f"| {name.replace('void lbm::', '')} | {spl} | {insts:.4g} | "
+                     f"{insts / (n ** 3 / 64 * spl):.0f} | {100 * busy:.0f}% | | |")
+    print("\n".join(lines))
+    return 0
+
+
 def trace_summary(trace_dir, bench_json):
     """Markdown table of a kernel trace of `python bench.py`, per kernel and
     box size, with the headline kernels' timed launches set against the
@@ -630,19 +688,57 @@ def trace_summary(trace_dir, bench_json):
                    f"{statistics.mean(v):.1f} | {min(v):.1f} | {max(v):.1f} | {100 * sum(v) / total:.1f}% |")
     steps, warm = d["steps"], d["warmup"]
     out.append("")
-    for key, label, ms in (("f32", "FP32", d["ms_per_step"]),
-                           ("f16", "FP16", d.get("f16_storage", {}).get("ms_per_step"))):
-        name = KERNELS[key][0]
+    two = d.get("roofline", {}).get("steps_per_launch") == 2
+    checks = [("f32x2" if two else "f32", "FP32 (headline)", d["ms_per_step"])]
+    if two:
+        checks.append(("f32", "FP32 single step", d.get("f32_single_step", {}).get("ms_per_step")))
+    checks.append(("f16", "FP16 single step", d.get("f16_storage", {}).get("ms_per_step")))
+    for key, label, ms in checks:
+        name, spl = KERNELS[key][0], KERNELS[key][4]
         n = round(d["config"]["cells"] ** (1 / 3))
         v = groups.get((name, launch_threads(name, n)), [])
-        if ms and len(v) >= steps + warm:
-            timed = v[warm:warm + steps]
-            out.append(f"{label}: the bench line reports {ms * 1e3:.1f} us per step (HIP events around "
-                       f"{steps} timed steps); the trace's {steps} launches after the {warm} warm-up "
-                       f"launches of {name.replace('void ', '')} at {n}^3 average "
-                       f"{statistics.mean(timed):.1f} us.")
+        wl, sl = warm // spl, steps // spl
+        if ms and len(v) >= wl + sl:
+            timed = v[wl:wl + sl]
+            per = f"{spl} steps per launch, " if spl > 1 else ""
+            out.append(f"{label}: the bench line reports {ms * spl * 1e3:.1f} us per launch "
+                       f"({per}HIP events around {steps} timed steps); the trace's {sl} launches "
+                       f"after the {wl} warm-up launches of {name.replace('void ', '')} at {n}^3 "
+                       f"average {statistics.mean(timed):.1f} us.")
     print("\n".join(out))
     return 0
+
+
+ROOFLINE_KERNELS = {  # leg -> kernel named in the roofline object
+    "f32": "k_step<F32, static walls, force, Qian>",
+    "f32x2": "k_step2<F32, static walls, force, Qian> (two steps per launch)",
+    "f16": "k_step<F16, static walls, force, Qian>",
+    "bf16": "k_step<BF16, static walls, force, Qian>",
+    "f64": "k_step<F64, static walls, force, Qian>",
+    "f32x": "k_step<F32X, static walls, force, Qian>",
+    "f16x2": "k_step2<F16, static walls, force, Qian> (two steps per launch)",
+    "bf16x2": "k_step2<BF16, static walls, force, Qian> (two steps per launch)",
+}
+
+
+def roofline_of(key, leg):
+    """The roofline object of one forward leg: algorithmic bytes per launch
+    (bytes per fluid-cell update x the updates one launch performs, plus the
+    flag bytes it reads) over the launch time measured with HIP events, and
+    the HBM bytes per launch from the committed counter summary."""
+    spl = leg["steps_per_launch"]
+    out = {"bound": "hbm", "achieved": leg["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": leg["hbm_frac"], "traffic": traffic_entry(key),
+           "kernel": ROOFLINE_KERNELS.get(key, key), "steps_per_launch": spl,
+           "alg_bytes_per_launch": spl * leg["alg_bytes_per_step"],
+           "launch_ms": spl * leg["ms_per_step"]}
+    if out["traffic"]:
+        out["traffic_over_alg"] = out["traffic"] / out["alg_bytes_per_launch"]
+    if spl == 2:
+        out["note"] = ("algorithmic bytes of two single-step updates (the intermediate level stays "
+                       "in LDS, so the kernel's HBM traffic is below them); the pass is bound by "
+                       "vector-instruction issue")
+    return out
 
 
 def main():
@@ -651,6 +747,8 @@ def main():
         return sweep_summary(args.sweep_summary)
     if args.trace_summary:
         return trace_summary(*args.trace_summary)
+    if args.valu_summary:
+        return valu_summary(*args.valu_summary)
     if args.profile_summary:
         return profile_summary(*args.profile_summary)
     if args.gpus != 1:
@@ -687,7 +785,7 @@ def main():
             res[st] = forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st,
                                   args.steps if head else aux, args.warmup, s,
                                   fields=fields if head else None,
-                                  clocks=clocks if st == "f32" else None,
+                                  clocks=clocks if st == "f32" and "f32x2" not in legs else None,
                                   pull=st in ("f32", "f16", "f64"))
             log(f"  {res[st]['mlups']:.0f} MLUPS, {res[st]['alg_gbs']:.0f} GB/s algorithmic")
     if "f32" in fields:
@@ -712,7 +810,8 @@ def main():
             if f"{st}x2" in legs:
                 log(f"forward {st}, two steps per pass")
                 res[f"{st}x2"] = forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st, args.steps,
-                                             args.warmup, s, steps_per_pass=2)
+                                             args.warmup, s, steps_per_pass=2,
+                                             clocks=clocks if st == "f32" else None)
                 log(f"  {res[f'{st}x2']['mlups']:.0f} MLUPS, {res[f'{st}x2']['alg_gbs']:.0f} GB/s "
                     "algorithmic")
     if "split" in legs:
@@ -749,8 +848,12 @@ def main():
         log("error against the oracle on its sample, every storage")
         res["error_vs_oracle"] = crop_error_leg(torch, *res["cpu"].pop("_state"))
 
-    main_leg = res.get("f32") or next((res[k] for k in ("f16", "bf16", "f64", "f32x") if k in res),
-                                      None)
+    # The headline is the fastest FP32 schedule: pairs of steps fused into one
+    # temporally blocked pass (bit-identical to single steps), else the
+    # single step, else the first other storage run.
+    main_key = next((k for k in ("f32x2", "f32", "f16", "bf16", "f64", "f32x") if k in res), None)
+    main_leg = res.get(main_key) if main_key else None
+    two = bool(main_leg) and main_leg["steps_per_launch"] == 2
     line = {
         "metric": "MLUPS & %HBM roofline, D3Q19 512^3 FP32 vs FP16-offset; adjoint/fwd time",
         "value": main_leg["mlups"] if main_leg else None,
@@ -765,27 +868,31 @@ def main():
         "config": {"workload": f"D3Q19 BGK porous periodic box {n}^3, 10% solid random spheres "
                                f"r 4-12 (seed 12345), tau 0.55, g_x 1e-6, from rest, "
                                f"{args.warmup + args.steps} steps ({args.steps} timed), "
-                               f"{main_leg['storage'] if main_leg else ''} offset storage",
+                               f"{main_leg['storage'] if main_leg else ''} offset storage"
+                               + (", two steps per pass (temporal blocking)" if two else ""),
                    "cells": n_cells, "fluid_cells": n_fluid},
     }
     if main_leg:
-        line["roofline"] = {
-            "bound": "hbm", "achieved": main_leg["alg_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": main_leg["hbm_frac"],
-            "traffic": traffic_entry(main_leg["alg_bytes_per_step"], main_leg["ms_per_step"]),
-            "kernel": "k_step<F32, static walls, force, Qian>",
-            "alg_bytes_per_launch": main_leg["alg_bytes_per_step"],
-        }
+        line["roofline"] = roofline_of(main_key, main_leg)
+    if two and "f32" in res:
+        # the single-step kernel on the same workload, with its own roofline
+        line["f32_single_step"] = dict(res["f32"], roofline=roofline_of("f32", res["f32"]))
     if "cpu" in res:
         line["cpu_baseline"] = res["cpu"]
     line["mflups"] = main_leg["mflups"] if main_leg else None
+    line["timing"] = main_leg["timing"] if main_leg else None
     for st in ("f16", "bf16", "f64", "f32x"):
         if st in res:
-            line[f"{st}_storage"] = res[st]
+            line[f"{st}_storage"] = dict(res[st], roofline=roofline_of(st, res[st]))
             if f"{st}_vs_f32" in res:
                 line[f"{st}_storage"]["vs_f32_same_step"] = res[f"{st}_vs_f32"]
     if "f16" in res and "f32" in res:
+        # same schedule (single steps), the fused pairs, and best against best
         line["f16_over_f32"] = res["f16"]["mlups"] / res["f32"]["mlups"]
+        if "f16x2" in res and "f32x2" in res:
+            line["f16_over_f32_two_steps_per_pass"] = res["f16x2"]["mlups"] / res["f32x2"]["mlups"]
+            line["f16_over_f32_best"] = (max(res["f16"]["mlups"], res["f16x2"]["mlups"])
+                                         / max(res["f32"]["mlups"], res["f32x2"]["mlups"]))
     if "adjoint" in res:
         line["adjoint"] = res["adjoint"]
         line["adjoint_256"] = res["adjoint_256"]
@@ -801,9 +908,10 @@ def main():
         line["cavity"] = res["cavity"]
     if "split" in res:
         line["split_obstacle_kernel"] = res["split"]
-    for st in ("f32", "f16", "bf16"):
+    for st in ("f16", "bf16"):
         if f"{st}x2" in res:
-            line[f"{st}_two_steps_per_pass"] = res[f"{st}x2"]
+            line[f"{st}_two_steps_per_pass"] = dict(res[f"{st}x2"],
+                                                    roofline=roofline_of(f"{st}x2", res[f"{st}x2"]))
     if "incomp" in res:
         line["incompressible_equilibrium"] = res["incomp"]
     if "error_vs_oracle" in res:
@@ -814,14 +922,18 @@ def main():
         line["copy_sweep"] = res["copy"]["sweep"]
         if main_leg:
             line["frac_of_copy_bw"] = main_leg["alg_gbs"] / res["copy"]["best"]["gbs"]
-    if main_leg and "pull_copy" in main_leg:
-        # the step's own access pattern without geometry or collision (lbm_pull_copy)
-        line["pull_copy_probe"] = dict(main_leg["pull_copy"])
+        if "f32_single_step" in line:
+            line["f32_single_step"]["frac_of_copy_bw"] = (res["f32"]["alg_gbs"]
+                                                          / res["copy"]["best"]["gbs"])
+    single = res.get("f32")
+    if single and "pull_copy" in single:
+        # the single step's own access pattern without geometry or collision (lbm_pull_copy)
+        line["pull_copy_probe"] = dict(single["pull_copy"])
     props = torch.cuda.get_device_properties(0)
     line["device"] = f"{props.name} ({getattr(props, 'gcnArchName', '?')}, "\
                      f"{props.multi_processor_count} CUs, {props.total_memory / 2**30:.0f} GiB)"
     line["hip_version"] = torch.version.hip
-    line["clocks_during_f32_leg"] = clocks or None
+    line["clocks_during_headline_leg"] = clocks or None
     line["context"] = "paper: 650 MLUPS SP / 290 MLUPS DP on an NVIDIA Tesla C2070 (other hardware)"
     print(json.dumps(line), flush=True)
     return 0

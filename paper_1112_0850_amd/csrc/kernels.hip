@@ -255,38 +255,15 @@ struct StepK {
   int moving;    // moving-wall markers in use (marker choice of WALLS = 3)
 };
 
-// Error-free transformations (exact in round-to-nearest binary floating
-// point): two_sum gives s = fl(a + b) and e with s + e = a + b exactly
-// (Knuth, TAOCP Vol. 2, Sec. 4.2.2); the product remainder fma(a, b, -fl(ab))
-// is exact as well (Ogita, Rump & Oishi, SIAM J. Sci. Comput. 26, 2005).
+// Fused multiply-add.  The product remainder fma(a, b, -fl(ab)) is exact in
+// round-to-nearest binary floating point (Ogita, Rump & Oishi, SIAM J. Sci.
+// Comput. 26, 2005).
 template <typename C>
 __device__ __forceinline__ C fmac(C a, C b, C c);
 template <>
 __device__ __forceinline__ float fmac<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 template <>
 __device__ __forceinline__ double fmac<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-template <typename C>
-__device__ __forceinline__ C two_sum(C a, C b, C& e) {
-  const C s = a + b;
-  const C bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
-  return s;
-}
-
-// c_i . (x, y, z) for compile-time i, with the rounding error of the one
-// addition of a diagonal direction returned in err (0 for an axis).
-template <typename C>
-__device__ __forceinline__ C cdot_exact(int i, C x, C y, C z, C& err) {
-  const C ax = D3Q19::cx[i] > 0 ? x : -x, ay = D3Q19::cy[i] > 0 ? y : -y,
-          az = D3Q19::cz[i] > 0 ? z : -z;
-  if (D3Q19::cx[i] == 0 && D3Q19::cy[i] == 0) { err = C(0); return az; }
-  if (D3Q19::cx[i] == 0 && D3Q19::cz[i] == 0) { err = C(0); return ay; }
-  if (D3Q19::cy[i] == 0 && D3Q19::cz[i] == 0) { err = C(0); return ax; }
-  if (D3Q19::cx[i] == 0) return two_sum(ay, az, err);
-  if (D3Q19::cy[i] == 0) return two_sum(ax, az, err);
-  return two_sum(ax, ay, err);
-}
 
 // BGK relaxation towards the Qian equilibrium with Guo forcing, in place, in
 // offset form with rho never formed (j' = j + F/2 = rho u):
@@ -304,44 +281,41 @@ __device__ __forceinline__ C cdot_exact(int i, C x, C y, C z, C& err) {
 // function of the smooth momentum field, so plain FP32 rounding of j' and of
 // omega a_i (c_i.j') recurs coherently from step to step and grows linearly
 // in time (8.7e-6 relative in u after 1000 steps of the porous 128^3 crop
-// against 2.3e-7 with the compensation; rounding of the stores alone, FP64
-// arithmetic, gives 7e-8).  The high part of the momentum term enters the
-// fused multiply-add with (1 - omega) g_i, whose rounding depends on the
-// population's own low bits; the low parts go in with the second-order
-// terms.
+// against 2.4e-7 with the compensation; rounding of the stores alone, FP64
+// arithmetic, gives 7e-8).  j' and, for the diagonal directions, c_i.j' are
+// summed in FP64 -- a difference of two FP32 populations is exact there
+// unless their magnitudes differ by more than 2^29, and the sums carry 53
+// bits -- and split into an FP32 head and the FP32 rounding of the exact
+// remainder (FP64 additions and conversions issue at the FP32 rate on this
+// GPU, so this costs fewer instructions than compensated FP32 sums).  The
+// high part of the momentum term enters the fused multiply-add with
+// (1 - omega) g_i, whose rounding depends on the population's own low bits;
+// the low parts go in with the second-order terms.
 template <typename C, bool FORCE, bool SCALED, bool INC, bool EXACT>
 __device__ __forceinline__ void collide(C* f, const StepK<C>& k, C fon) {
   const C drho = delta_rho(f);
   C jx, jy, jz, lx = C(0), ly = C(0), lz = C(0);
+  double Jx = 0, Jy = 0, Jz = 0;
   if (EXACT) {
-    // d_p + e_p = g_(2p+1) - g_(2p+2) exactly; pairs p = 0..8 are the
-    // directions x, y, z, x+y, x-y, x+z, x-z, y+z, y-z.
-    C d[9], e[9], t0, t1, t2, t3;
+    // j' in FP64, then head + tail: the FP32 rounding of J and the FP32
+    // rounding of the exact remainder J - head.
+    double d[9];
 #pragma unroll
-    for (int p = 0; p < 9; ++p) d[p] = two_sum(f[2 * p + 1], -f[2 * p + 2], e[p]);
-    C s = two_sum(d[0], d[3], t0);
-    s = two_sum(s, d[4], t1);
-    s = two_sum(s, d[5], t2);
-    jx = two_sum(s, d[6], t3);
-    lx = (((e[0] + e[3]) + (e[4] + e[5])) + e[6]) + ((t0 + t1) + (t2 + t3));
-    s = two_sum(d[1], d[3], t0);
-    s = two_sum(s, -d[4], t1);
-    s = two_sum(s, d[7], t2);
-    jy = two_sum(s, d[8], t3);
-    ly = (((e[1] + e[3]) - (e[4] - e[7])) + e[8]) + ((t0 + t1) + (t2 + t3));
-    s = two_sum(d[2], d[5], t0);
-    s = two_sum(s, -d[6], t1);
-    s = two_sum(s, d[7], t2);
-    jz = two_sum(s, -d[8], t3);
-    lz = (((e[2] + e[5]) - (e[6] - e[7])) - e[8]) + ((t0 + t1) + (t2 + t3));
+    for (int p = 0; p < 9; ++p) d[p] = double(f[2 * p + 1]) - double(f[2 * p + 2]);
+    Jx = (((d[0] + d[3]) + (d[4] + d[5])) + d[6]);
+    Jy = (((d[1] + d[3]) - (d[4] - d[7])) + d[8]);
+    Jz = (((d[2] + d[5]) - (d[6] - d[7])) - d[8]);
     if (FORCE) {
-      jx = two_sum(jx, fon * k.Fh[0], t0);
-      jy = two_sum(jy, fon * k.Fh[1], t1);
-      jz = two_sum(jz, fon * k.Fh[2], t2);
-      lx += t0;
-      ly += t1;
-      lz += t2;
+      Jx += double(fon * k.Fh[0]);
+      Jy += double(fon * k.Fh[1]);
+      Jz += double(fon * k.Fh[2]);
     }
+    jx = C(Jx);
+    jy = C(Jy);
+    jz = C(Jz);
+    lx = C(Jx - double(jx));
+    ly = C(Jy - double(jy));
+    lz = C(Jz - double(jz));
   } else {
     const C d1 = f[1] - f[2], d3 = f[3] - f[4], d5 = f[5] - f[6], d7 = f[7] - f[8],
             d9 = f[9] - f[10], d11 = f[11] - f[12], d13 = f[13] - f[14], d15 = f[15] - f[16],
@@ -379,9 +353,23 @@ __device__ __forceinline__ void collide(C* f, const StepK<C>& k, C fon) {
     const int i = 2 * p + 1, c = speed_class(i);
     const C eu = cdot<C>(i, ux, uy, uz);
     if (EXACT) {
-      C el;
-      const C ej = cdot_exact<C>(i, jx, jy, jz, el);
-      el += cdot<C>(i, lx, ly, lz);
+      C ej, el;
+      if (D3Q19::cx[i] != 0 && D3Q19::cy[i] != 0) {
+        const double J = (D3Q19::cx[i] > 0 ? Jx : -Jx) + (D3Q19::cy[i] > 0 ? Jy : -Jy);
+        ej = C(J);
+        el = C(J - double(ej));
+      } else if (D3Q19::cx[i] != 0 && D3Q19::cz[i] != 0) {
+        const double J = (D3Q19::cx[i] > 0 ? Jx : -Jx) + (D3Q19::cz[i] > 0 ? Jz : -Jz);
+        ej = C(J);
+        el = C(J - double(ej));
+      } else if (D3Q19::cy[i] != 0 && D3Q19::cz[i] != 0) {
+        const double J = (D3Q19::cy[i] > 0 ? Jy : -Jy) + (D3Q19::cz[i] > 0 ? Jz : -Jz);
+        ej = C(J);
+        el = C(J - double(ej));
+      } else {
+        ej = cdot<C>(i, jx, jy, jz);
+        el = cdot<C>(i, lx, ly, lz);
+      }
       C sym = k.oc[c] * (ej * eu) + oWb[c];
       // omega a ej = hi + lo: two rounded products and their exact remainders
       const C p1 = k.a[c] * ej;
@@ -575,10 +563,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 // chip.  The 16 populations that move in x or y go through a ring of LDS
 // plane-arrays over the halo-extended tile, each value stored at the cell
 // that pulls it (A_i[x + c_i] = f*_i(x)): a step-2 read of direction i is
-// A_i at the cell's own index, and the own cell's value of direction j,
-// which a bounce-back needs, is A_j[x + c_j].  The three populations that do
-// not move in x or y (0 and the pure-z pair) stay in the registers of the
-// thread that owns the column.  The ring holds as many planes of a direction
+// A_i at the cell's own index.  The own cell's intermediate values, which a
+// step-2 bounce-back needs, are the thread's own step-1 results of the
+// previous plane and stay in its registers (an LDS read there would wait
+// behind the marker test of the pulled value); so do the three populations
+// that do not move in x or y (0 and the pure-z pair).  The ring holds as many planes of a direction
 // as they are read: c_z = +1 two planes later (3 slots), c_z = 0 and c_z =
 // -1 up to one plane later (2 slots); two barriers per plane separate writes
 // from reads.  The next plane's 19 pulls are issued before the first barrier,
@@ -593,15 +582,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 constexpr int kTB2Arrays = 36;  // LDS plane-arrays of [TY + 2][66]
 constexpr int kTB2Chunk = 128;  // z planes per block
 
-// Tile rows per block.  With the pulls addressed as one wave-uniform base
-// plus 32-bit offsets the kernel fits 128 VGPRs (114 for 4-byte, 88 for
-// 2-byte storage) without spills, so 13 rows (16 waves, 1024 threads) fit;
-// measured at 512^3 with 4-byte storage 13 rows beat 8 by 13%, 2-byte
-// storage runs the same with either.  8-byte storage takes 4 so that its
-// ring fits in LDS.
-template <typename T>
+// Tile rows per block: 13 (16 waves, 1024 threads, one block per CU: the
+// FP32 ring takes 143 KB of LDS) for 4- and 2-byte storage, which fit 128
+// VGPRs without spills; measured at 512^3, 13 rows beat 12, 8, 6 and 5.
+// FP64 storage takes 4 so that its ring fits in LDS, and F32X (FP64
+// arithmetic) 8, whose 11 waves may use 168 VGPRs.
+template <int K>
 __host__ __device__ constexpr int tb2_rows() {
-  return sizeof(T) >= 8 ? 4 : 13;
+  return K == ST_F64 ? 4 : (K == ST_F32X ? 8 : 13);
 }
 __host__ __device__ constexpr int tb2_nslot(int i) { return D3Q19::cz[i] > 0 ? 3 : 2; }
 // first plane-array of direction i (the 16 directions with c_x or c_y != 0)
@@ -662,12 +650,12 @@ __device__ __forceinline__ void store_nt_at(uint64_t base, uint32_t off, T v) {
 }
 
 template <int K, int WALLS, bool FORCE, bool INC>
-__global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void k_step2(
+__global__ __launch_bounds__(64 * (tb2_rows<K>() + 3)) void k_step2(
     const typename Storage<K>::T* __restrict__ src, typename Storage<K>::T* __restrict__ dst,
     const uint8_t* __restrict__ flags, Geo2 g, StepK<typename Storage<K>::C> k) {
   using C = typename Storage<K>::C;
   using T = typename Storage<K>::T;
-  constexpr int TY = tb2_rows<T>(), TX = 64, EX = TX + 2, EY = TY + 2;
+  constexpr int TY = tb2_rows<K>(), TX = 64, EX = TX + 2, EY = TY + 2;
   constexpr uint32_t SZ = sizeof(T);
   constexpr uint32_t PLB = uint32_t(EY * EX) * SZ;  // bytes of one LDS plane-array
   constexpr bool SOLIDS = WALLS >= 1;
@@ -733,7 +721,9 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
     nfl = SOLIDS ? flags[uint32_t(pz) * fl_z + fl_yx] : uint8_t(0);
   };
   // own column's step-1 results: planes p - 1 (prev) and p - 2 (pp5)
-  T prev0 = T(0), prev5 = T(0), prev6 = T(0), pp5 = T(0);
+  T prevv[Q], pp5 = T(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) prevv[i] = T(0);
   uint8_t fl_prev = 0;
   issue(z0 - 1);
   for (int p = z0 - 1; p <= zend; ++p) {
@@ -774,16 +764,14 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
       collide<C, FORCE, K == ST_F16, INC, K == ST_F32>(f, k, C(1));
     const T marker = solid_marker<K>(fl, WALLS == 2);
     const uint32_t w2 = phase_base(p, 2), w3 = phase_base(p, 3);
-    T cur0, cur5, cur6;
+    T cur[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       C o = f[i];
       if constexpr (K == ST_F16) o = fp32_result(o);
       const T v = solid ? marker : T(o);
-      if (i == 0) cur0 = v;
-      else if (i == 5) cur5 = v;
-      else if (i == 6) cur6 = v;
-      else {
+      cur[i] = v;
+      if (i != 0 && i != 5 && i != 6) {
         const int tx = ex + D3Q19::cx[i], ty = ey + D3Q19::cy[i];
         if (tx >= -1 && tx <= TX && ty >= -1 && ty <= TY)
           ring_at(tb2_nslot(i) == 3 ? w3 : w2, i, D3Q19::cy[i], D3Q19::cx[i]) = v;
@@ -797,24 +785,19 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
       const uint32_t qownb = uint32_t(wrap_mod(q, g.nz)) * zstride + own_yx;
       const bool solid2 = SOLIDS && (fl_prev & FLAG_SOLID);
       // plane q - c_z of direction i: p - 2 (c_z = +1, 3 slots), p - 1, p
-      const uint32_t r3 = phase_base(p - 2, 3), r2 = phase_base(q, 2), b3 = phase_base(q, 3);
+      const uint32_t r3 = phase_base(p - 2, 3), r2 = phase_base(q, 2);
       C h[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         T w;
-        if (i == 0) w = prev0;
+        if (i == 0) w = prevv[0];
         else if (i == 5) w = pp5;
-        else if (i == 6) w = cur6;
+        else if (i == 6) w = cur[6];
         else w = ring_at(D3Q19::cz[i] > 0 ? r3 : (D3Q19::cz[i] == 0 ? r2 : w2), i, 0, 0);
         h[i] = C(w);
         if (MARKERS && i != 0 && is_marker<K, WALLS>(raw_bits<K>(w)) && !solid2) {
           // half-way bounce-back: the own cell's opposite population at plane q
-          const int j = D3Q19::opp[i];
-          T bt;
-          if (j == 5) bt = prev5;
-          else if (j == 6) bt = prev6;
-          else bt = ring_at(tb2_nslot(j) == 3 ? b3 : r2, j, D3Q19::cy[j], D3Q19::cx[j]);
-          C bb = C(bt);
+          C bb = C(prevv[D3Q19::opp[i]]);  // this thread's own step-1 output at plane q
           if (WALLS == 2 && raw_bits<K>(w) == Storage<K>::kMoving) bb += k.Kw[i];
           h[i] = bb;
         }
@@ -836,10 +819,9 @@ __global__ __launch_bounds__(64 * (tb2_rows<typename Storage<K>::T>() + 3)) void
       }
     }
     __syncthreads();
-    pp5 = prev5;
-    prev0 = cur0;
-    prev5 = cur5;
-    prev6 = cur6;
+    pp5 = prevv[5];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) prevv[i] = cur[i];
     fl_prev = fl;
   }
 }
@@ -1537,7 +1519,7 @@ template <int K, int WALLS, bool FORCE, bool INC>
 static void step2_t(const Geo& g, const PhysParams& ph, const void* src, void* dst,
                     const uint8_t* flags, hipStream_t s) {
   using S = Storage<K>;
-  constexpr int rows = tb2_rows<typename S::T>();
+  constexpr int rows = tb2_rows<K>();
   const Geo2 h = make_geo2(g, rows);
   hipLaunchKernelGGL((k_step2<K, WALLS, FORCE, INC>), dim3(h.nblocks), dim3(64 * (rows + 3)), 0,
                      s, reinterpret_cast<const typename S::T*>(src),

@@ -40,7 +40,7 @@ def test_traffic_is_null_for_other_code(tmp_path, monkeypatch):
     src = tmp_path / "k.hip"
     src.write_text("int g() { return 3; }\n")
     monkeypatch.setattr(b, "KERNEL_SRCS", [str(src)])
-    assert b.traffic_entry(1, 1.0) is None
+    assert b.traffic_entry("f32") is None
 
 
 def test_gpu_clocks_from_dpm_tables(tmp_path, monkeypatch):
@@ -85,6 +85,56 @@ def test_trace_summary_against_the_bench_line(tmp_path, capsys):
     out = capsys.readouterr().out
     assert "| lbm::k_step<0, 1, true, false, 1> | 512^3 | 6 | 3.7 | 3.0 | 5.0 |" in out
     assert "4 launches after the 2 warm-up launches" in out and "average 3.0 us" in out
+
+
+def test_repetition_sizes_keep_whole_launches():
+    b = _bench()
+    assert b.rep_sizes(980, 5) == [196] * 5
+    assert b.rep_sizes(980, 5, unit=2) == [196] * 5
+    assert b.rep_sizes(25, 5, unit=2) == [6, 6, 4, 4, 5]  # 12 pairs, the odd step last
+    assert b.rep_sizes(3, 5, unit=2) == [3]
+    assert b.rep_sizes(1, 5, unit=2) == [1]
+    assert sum(b.rep_sizes(1001, 5, unit=2)) == 1001
+
+
+def test_trace_summary_two_steps_per_launch(tmp_path, capsys):
+    """A headline of two steps per launch is checked against the two-step
+    kernel's launches: warm-up and timed steps count in pairs."""
+    b = _bench()
+    k2 = "void lbm::k_step2<0, 1, true, false>"
+    g = b.launch_threads(k2, 512)
+    assert b.box_of(k2, g) == 512
+    cols = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X"]
+    lines, t = [",".join(cols)], 0
+    for k in range(5):  # 1 warm-up launch of 9 us, then 4 timed launches of 6 us
+        dur = 9000 if k < 1 else 6000
+        lines.append(f'"{k2}(args)",{t},{t + dur},{g}')
+        t += dur + 100
+    (tmp_path / "x_kernel_trace.csv").write_text("\n".join(lines) + "\n")
+    line = {"steps": 8, "warmup": 2, "ms_per_step": 0.003, "config": {"cells": 512 ** 3},
+            "roofline": {"steps_per_launch": 2}}
+    (tmp_path / "b.json").write_text(json.dumps(line) + "\n")
+    assert b.trace_summary(str(tmp_path), str(tmp_path / "b.json")) == 0
+    out = capsys.readouterr().out
+    assert "6.0 us per launch (2 steps per launch" in out
+    assert "4 launches after the 1 warm-up launches" in out and "average 6.0 us" in out
+
+
+def test_roofline_of_two_step_leg(tmp_path, monkeypatch):
+    """Algorithmic bytes per launch are those of the updates the launch
+    performs; traffic comes from the counter record of the same kernel."""
+    b = _bench()
+    monkeypatch.setattr(b, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    json.dump({"code_sha256": b.code_hash(),
+               "kernels": {"f32x2": {"fetch_bytes": 6e9, "write_bytes": 4e9}}},
+              open(tmp_path / "traffic.json", "w"))
+    leg = {"steps_per_launch": 2, "alg_gbs": 6800.0, "hbm_frac": 0.85,
+           "alg_bytes_per_step": 1.0e10, "ms_per_step": 1.5}
+    r = b.roofline_of("f32x2", leg)
+    assert r["alg_bytes_per_launch"] == 2.0e10 and r["launch_ms"] == 3.0
+    assert r["traffic"] == 1.0e10 and r["traffic_over_alg"] == 0.5
+    assert r["frac"] == 0.85 and r["bound"] == "hbm" and "note" in r
+    assert b.roofline_of("f16", dict(leg, steps_per_launch=1))["traffic"] is None
 
 
 def test_profile_summary_calibrates_and_records(tmp_path, monkeypatch, capsys):
