@@ -158,7 +158,10 @@ typedef struct {
 
 typedef struct lbm_ctx lbm_ctx;
 
-/* Sizes the caller must allocate for `p` (any output pointer may be NULL):
+/* Sizes the caller must allocate for `p` (any output pointer may be NULL).
+ * The layout is the structure of arrays of Sec. 6 (one array per direction,
+ * x fastest) with each row padded as Sec. 6 pads for aligned access, here to
+ * x_align cells:
  *   x_stride       padded x extent of a grid row, in cells;
  *   dir_stride     elements from one direction array to the next;
  *   grid_bytes     bytes of ONE population grid (two are needed);
@@ -219,6 +222,8 @@ lbm_status lbm_step(lbm_ctx* ctx, int32_t n);
 lbm_status lbm_step_from(lbm_ctx* ctx, const void* src, void* dst);
 
 /* Macroscopic fields of the current time level t from the stored f*(t):
+ * the moments of Sec. 2 (density and momentum as the zeroth and first
+ * moments of the populations, the quantities of the collision step),
  * rho = sum f*_i, rho u = sum f*_i c_i - F/2 (equal to the pre-collision
  * moments of step t under Guo forcing; F = 0 on no-force cells; rho0 u with
  * rho0 = 1 for the incompressible equilibrium).  Solid

@@ -160,3 +160,81 @@ def test_two_step_pass_cavity_at_full_size():
     assert _same(one, two)
     del one, two
     torch.cuda.empty_cache()
+
+
+def _sampled_two_steps(sim, flags, cells, tau, F, extra=2):
+    """`extra` steps, then one fused pass of two: each sampled fluid cell
+    against the oracle's two steps of its 5^3 neighbourhood, read from the
+    state before the pass (the centre after two steps depends on that
+    neighbourhood only; no copy of the grid, so one box fills the GPU)."""
+    nz, ny, nx = sim.shape
+    sim.step(extra)
+    torch.cuda.synchronize()
+    pv = sim.populations()
+    crops = []
+    for c in cells:
+        z, rem = divmod(int(c), ny * nx)
+        y, x = divmod(rem, nx)
+        zi = torch.tensor([(z + d) % nz for d in range(-2, 3)], device=pv.device)
+        yi = torch.tensor([(y + d) % ny for d in range(-2, 3)], device=pv.device)
+        xi = torch.tensor([(x + d) % nx for d in range(-2, 3)], device=pv.device)
+        g = pv[:, zi[:, None, None], yi[None, :, None], xi[None, None, :]].double().cpu().numpy()
+        fl = np.ascontiguousarray(flags[np.ix_([(z + d) % nz for d in range(-2, 3)],
+                                               [(y + d) % ny for d in range(-2, 3)],
+                                               [(x + d) % nx for d in range(-2, 3)])])
+        crops.append((z, y, x, g, fl))
+    t0 = sim.t
+    sim.step(2)
+    torch.cuda.synchronize()
+    assert sim.t == t0 + 2
+    cv = sim.populations()
+    _, w, _ = O.lattice()
+    worst = 0.0
+    for z, y, x, g, fl in crops:
+        f = g + w[:, None, None, None]
+        f[:, fl & 1 == 1] = 0
+        ref = O.step(f, tau, F, fl, n=2)[:, 2, 2, 2] - w
+        got = cv[:, z, y, x].double().cpu().numpy()
+        err = np.abs(got - ref)
+        bound = 1e-6 * np.abs(ref).max() + 1e-12
+        worst = max(worst, float(err.max()))
+        assert (err <= bound).all(), (z, y, x, err.max(), bound)
+    say(f"  worst error {worst:.2e}")
+
+
+def test_two_step_pass_large_box():
+    """The large-box workload (768^3, 5% spheres r 4-12, seed 777, tau 0.55,
+    g_x 1e-6; 68.9 GB FP32) in fused pairs: sampled cells against the
+    oracle."""
+    n = 768
+    say(f"two-step pass at {n}^3 porous f32: sampled parity")
+    flags = I.sphere_pack((n, n, n), 0.05, seed=777)
+    u0 = I.shear_waves((n, n, n), seed=5, amplitude=0.02)
+    u0[:, flags & 1 == 1] = 0
+    sim = LBM((n, n, n), 0.55, (1e-6, 0, 0), "f32", flags=flags, u0=torch.from_numpy(u0),
+              steps_per_pass=2)
+    del u0
+    rng = np.random.default_rng(7682)
+    fluid = np.flatnonzero((flags & 1 == 0).ravel())
+    _sampled_two_steps(sim, flags, rng.choice(fluid, size=96, replace=False), 0.55, (1e-6, 0, 0))
+    del sim
+    torch.cuda.empty_cache()
+
+
+def test_two_step_pass_at_maximum_size():
+    """The largest FP32 box the 32-bit offsets allow (1023^3, one direction
+    array just under 4 GiB), a channel with walls at y = 0 and y = 1022, in
+    fused pairs: cells near the far end of the arrays, where the byte offsets
+    are largest, at the tile and chunk edges, and at random."""
+    n = 1023
+    say(f"two-step pass at {n}^3 channel f32: sampled parity")
+    flags = I.channel_flags((n, n, n))
+    sim = LBM((n, n, n), 0.55, (1e-6, 0, 0), "f32", flags=flags, steps_per_pass=2)
+    rng = np.random.default_rng(10232)
+    zyx = [(n - 1, n - 2, n - 1), (n - 1, 1, 0), (n - 2, n - 2, n - 2), (0, 1, 0), (127, 13, 63),
+           (128, 14, 64), (1022, 1021, 1022), (896, 1015, 960)]
+    zyx += [(int(z), int(y), int(x)) for z, y, x in
+            zip(rng.integers(0, n, 40), rng.integers(1, n - 1, 40), rng.integers(0, n, 40))]
+    _sampled_two_steps(sim, flags, [(z * n + y) * n + x for z, y, x in zyx], 0.55, (1e-6, 0, 0))
+    del sim
+    torch.cuda.empty_cache()
