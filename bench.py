@@ -241,7 +241,7 @@ def sweep(torch, storages=("f32", "f16", "f64"), sizes=SWEEP_N):
     point: the median of 5 timed repetitions (timed_steps); when N is a
     multiple of 64 both layouts are the same and the point is timed once.
     Up to N = 160 the padded layout is also timed with replayed graphs of
-    32 steps."""
+    32 steps, and every padded point once more with two steps per pass."""
     from paper_1112_0850_amd.lbm import LBM
     for st in storages:
         for n in sizes:
@@ -260,15 +260,22 @@ def sweep(torch, storages=("f32", "f16", "f64"), sizes=SWEEP_N):
                     sim.use_graphs(32)
                     msg = timed_steps(sim, torch, 320, 64)
                     rec["graph_mlups"] = n ** 3 / msg / 1e3
-                print(json.dumps(rec), flush=True)
                 del sim
+                if align == 0:  # the same box in fused pairs of steps
+                    sim = LBM((n, n, n), 0.6, (0.0, 0.0, 0.0), st, steps_per_pass=2)
+                    ms2 = timed_steps(sim, torch, steps + steps % 2, max(4, steps // 10 * 2),
+                                      unit=2)
+                    rec["two_step_mlups"] = n ** 3 / ms2 / 1e3
+                    del sim
+                print(json.dumps(rec), flush=True)
             torch.cuda.empty_cache()
     return 0
 
 
 def sweep_summary(path):
     """Markdown table of the JSON lines `--sweep` printed (MLUPS, padded /
-    unpadded, per storage and edge N)."""
+    unpadded, with graphs where timed, and the padded box in fused pairs of
+    steps, per storage and edge N)."""
     rows = [json.loads(l) for l in open(path) if l.startswith("{")]
     sts = sorted({r["sweep"] for r in rows}, key=["f32", "f16", "bf16", "f64"].index)
     ns = sorted({r["n"] for r in rows})
@@ -284,6 +291,8 @@ def sweep_summary(path):
                 c += f" / {unp[0]['mlups'] / 1e3:.1f}k"
             if pad and "graph_mlups" in pad[0]:
                 c += f" (graphs {pad[0]['graph_mlups'] / 1e3:.1f}k)"
+            if pad and "two_step_mlups" in pad[0]:
+                c += f"; two steps per pass {pad[0]['two_step_mlups'] / 1e3:.1f}k"
             cells.append(c)
         out.append(f"| {n} | " + " | ".join(cells) + " |")
     print("\n".join(out))
@@ -536,19 +545,27 @@ KERNELS = {  # record key -> (kernel name, box edge, bytes per fluid update, por
 def launch_threads(name, n):
     """Threads a launch of the named kernel has on an n^3 box (64 * M-cell
     segments per row, four per block, M = 4 for the 16-bit step kernels; the
-    two-step kernel: 64 x TY tiles (TY = 13; 4 for FP64, 8 for F32X) and
-    128-plane z chunks, 64 (TY + 3) threads per block)."""
+    two-step kernel: 64 x TY tiles (TY = 13; 4 for FP64, 8 for F32X), z
+    chunks of 128 planes halved down to 16 until there are 1280 blocks,
+    64 (TY + 3) threads per block)."""
     if name.startswith("void lbm::k_step2<"):
         k = int(name.split("<")[1].split(",")[0])
         ty = {3: 4, 4: 8}.get(k, 13)
-        return -(-n // 64) * -(-n // ty) * -(-n // min(n, 128)) * 64 * (ty + 3)
+        tiles = -(-n // 64) * -(-n // ty)
+        zc = min(n, 128)
+        while zc > 16 and tiles * -(-n // zc) < 1280:
+            zc = max(zc // 2, 16)
+        return tiles * -(-n // zc) * 64 * (ty + 3)
     m = 4 if name.startswith("void lbm::k_step<1,") or name.startswith("void lbm::k_step<2,") else 1
     nseg = -(-n // (64 * m))
     return -(-nseg * n * n // 4) * 256
 
 
 def box_of(name, grid):
-    return next((n for n in (128, 256, 512, 640, 768) if launch_threads(name, n) == grid), None)
+    """The box edge of a launch from its grid size, trying the bench's own
+    sizes first (the two-step kernel's launches at 256^3 and 512^3 have the
+    same size: 1280 blocks)."""
+    return next((n for n in (512, 768, 640, 256, 128) if launch_threads(name, n) == grid), None)
 
 
 def profile_summary(trace_dir, fetch_dir, write_dir, n=512):

@@ -580,7 +580,9 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 // and one write of f*(t+2) -- about half of two single steps.
 // ---------------------------------------------------------------------------
 constexpr int kTB2Arrays = 36;  // LDS plane-arrays of [TY + 2][66]
-constexpr int kTB2Chunk = 128;  // z planes per block
+constexpr int kTB2Chunk = 128;     // longest z chunk (planes per block)
+constexpr int kTB2MinChunk = 16;   // shortest z chunk
+constexpr int kTB2MinBlocks = 1280;  // five blocks per CU on 256 CUs
 
 // Tile rows per block: 13 (16 waves, 1024 threads, one block per CU: the
 // FP32 ring takes 143 KB of LDS) for 4- and 2-byte storage, which fit 128
@@ -1508,7 +1510,15 @@ static Geo2 make_geo2(const Geo& g, int rows) {
   h.plane = g.plane;
   h.ntx = (g.nx + 63) / 64;
   h.nty = (g.ny + rows - 1) / rows;
+  // The longest z chunk (128, 64, 32, 16 planes) that still gives at least
+  // kTB2MinBlocks blocks, else 16: a chunk recomputes two planes of step 1,
+  // and fewer blocks than five per CU leave CUs idle (measured on periodic
+  // cubes: 256^3 runs 45.0k MLUPS FP32 with 128-plane chunks, 160 blocks,
+  // and 56.9k with 16-plane chunks, 1280 blocks; 512^3 runs best with 128).
   h.zc = g.nz < kTB2Chunk ? g.nz : kTB2Chunk;
+  while (h.zc > kTB2MinChunk &&
+         int64_t(h.ntx) * h.nty * ((g.nz + h.zc - 1) / h.zc) < kTB2MinBlocks)
+    h.zc = h.zc / 2 > kTB2MinChunk ? h.zc / 2 : kTB2MinChunk;
   const int nzc = (g.nz + h.zc - 1) / h.zc;
   h.nblocks = h.ntx * h.nty * nzc;
   h.nb8 = (h.nblocks / 8) * 8;
