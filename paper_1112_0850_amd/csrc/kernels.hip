@@ -567,10 +567,10 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 // step-2 bounce-back needs, are the thread's own step-1 results of the
 // previous plane and stay in its registers (an LDS read there would wait
 // behind the marker test of the pulled value); so do the three populations
-// that do not move in x or y (0 and the pure-z pair).  The ring holds as many planes of a direction
-// as they are read: c_z = +1 two planes later (3 slots), c_z = 0 and c_z =
-// -1 up to one plane later (2 slots); two barriers per plane separate writes
-// from reads.  The next plane's 19 pulls are issued before the first barrier,
+// that do not move in x or y (0 and the pure-z pair).  The ring holds as
+// many planes of a direction as they are read: c_z = +1 two planes later
+// (3 slots), c_z = 0 and c_z = -1 up to one plane later (2 slots); two
+// barriers per plane separate writes from reads.  The next plane's 19 pulls are issued before the first barrier,
 // so their latency hides behind step 2.  Both steps run the single-step
 // kernel's pull, marker test, collision and rounding, and the intermediate
 // values are rounded to the storage type, so a pass equals two single steps
@@ -601,12 +601,7 @@ __host__ __device__ constexpr int tb2_base(int i) {
     if (D3Q19::cx[j] != 0 || D3Q19::cy[j] != 0) b += tb2_nslot(j);
   return b;
 }
-// plane-array of direction i holding plane p (p may be negative)
-__device__ __forceinline__ int tb2_slot(int i, int p) {
-  const int ns = tb2_nslot(i);
-  const int r = p % ns;
-  return tb2_base(i) + (r < 0 ? r + ns : r);
-}
+static_assert(tb2_base(Q) == kTB2Arrays, "ring plane-arrays");
 
 __device__ __forceinline__ int wrap_mod(int v, int n) {
   const int r = v % n;
@@ -662,6 +657,7 @@ __global__ __launch_bounds__(64 * (tb2_rows<K>() + 3)) void k_step2(
   constexpr uint32_t PLB = uint32_t(EY * EX) * SZ;  // bytes of one LDS plane-array
   constexpr bool SOLIDS = WALLS >= 1;
   constexpr bool MARKERS = WALLS >= 1;
+  static_assert(sizeof(T) * kTB2Arrays * EY * EX <= 160 * 1024, "ring exceeds the LDS of a CU");
   __shared__ T ring[kTB2Arrays * EY * EX];
   // block -> tile: x tiles fastest, then y tiles, then z chunks; XCD k gets
   // the k-th contiguous eighth of that order
