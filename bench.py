@@ -656,7 +656,7 @@ def valu_summary(trace_dir, counter_dir, n=512, simds=1024, xcds=8):
         name = r["Kernel_Name"].split("(")[0]
         if not name.startswith("void lbm::k_step"):
             continue
-        key = (name if name.startswith("void ") else name, int(r["Grid_Size"]))
+        key = (name, int(r["Grid_Size"]))
         cnt.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     times = {}
     for r in csv.DictReader(open(glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0])):
