@@ -69,6 +69,10 @@ def parse():
                     help="summarise a rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU "
                          "SQ_BUSY_CYCLES GRBM_GUI_ACTIVE pass of this script (vector-instruction "
                          "issue of the step kernels at the porous 512^3 box) as markdown and exit")
+    ap.add_argument("--stall-summary", nargs=1, metavar="COUNTER_DIR",
+                    help="summarise a rocprofv3 --pmc SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY "
+                         "SQ_ACTIVE_INST_ANY ... pass of this script (where the step kernels' "
+                         "waves spend their time at the porous 512^3 box) as markdown and exit")
     return ap.parse_args()
 
 
@@ -684,6 +688,39 @@ def valu_summary(trace_dir, counter_dir, n=512, simds=1024, xcds=8):
     return 0
 
 
+def stall_summary(counter_dir, n=512):
+    """Where the step kernels' waves spend their time at the n^3 box: the
+    shares of SQ_WAVE_CYCLES (wave-cycles resident) spent waiting on a
+    dependency (SQ_WAIT_ANY: loads, LDS, barriers), ready but not issued
+    (SQ_WAIT_INST_ANY) and issuing (SQ_ACTIVE_INST_ANY), averaged over the
+    dispatches of each kernel."""
+    import csv
+    import glob
+    import statistics
+    cnt = {}
+    for r in csv.DictReader(open(glob.glob(os.path.join(counter_dir, "*counter_collection.csv"))[0])):
+        name = r["Kernel_Name"].split("(")[0]
+        if not name.startswith("void lbm::k_step"):
+            continue
+        cnt.setdefault((name, int(r["Grid_Size"])), {}).setdefault(
+            r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    lines = ["| kernel | waiting on a dependency | ready, not issued | issuing | LDS bank conflicts "
+             "per LDS instruction-cycle |", "|---|---|---|---|---|"]
+    for (name, grid), c in sorted(cnt.items()):
+        need = ("SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY")
+        if box_of(name, grid) != n or not all(k in c for k in need):
+            continue
+        m = {k: statistics.mean(v) for k, v in c.items()}
+        w = m["SQ_WAVE_CYCLES"]
+        lds = (f"{m['SQ_LDS_BANK_CONFLICT'] / m['SQ_ACTIVE_INST_LDS']:.3f}"
+               if m.get("SQ_ACTIVE_INST_LDS") else "")
+        lines.append(f"| {name.replace('void lbm::', '')} | {100 * m['SQ_WAIT_ANY'] / w:.0f}% | "
+                     f"{100 * m['SQ_WAIT_INST_ANY'] / w:.0f}% | "
+                     f"{100 * m['SQ_ACTIVE_INST_ANY'] / w:.0f}% | {lds} |")
+    print("\n".join(lines))
+    return 0
+
+
 def trace_summary(trace_dir, bench_json):
     """Markdown table of a kernel trace of `python bench.py`, per kernel and
     box size, with the headline kernels' timed launches set against the
@@ -770,6 +807,8 @@ def main():
         return trace_summary(*args.trace_summary)
     if args.valu_summary:
         return valu_summary(*args.valu_summary)
+    if args.stall_summary:
+        return stall_summary(*args.stall_summary)
     if args.profile_summary:
         return profile_summary(*args.profile_summary)
     if args.gpus != 1:
