@@ -3,10 +3,12 @@
 
 Workload (the headline): porous periodic box 512^3, 10% solid from random
 non-overlapping spheres of radius 4-12 (seed 12345), tau = 0.55, body force
-g_x = 1e-6, fluid initially at rest; FP32 offset storage.  One "step" is one
-fused stream-collide update of the whole box (one kernel launch).  Reported
-beside it, on the same geometry: FP16-offset and BF16-offset storage (FP32
-collide) and FP64 storage; the adjoint/forward time ratio of the
+g_x = 1e-6, fluid initially at rest; FP32 offset storage, pairs of steps
+fused into one temporally blocked pass (bit-identical to single steps).  One
+"step" is one stream-collide update of the whole box (a launch performs two).
+Reported beside it, on the same geometry: the single-step kernel, FP16-offset
+and BF16-offset storage (FP32 collide) and FP64 storage, one and two steps
+per pass; the adjoint/forward time ratio of the
 differentiable rollout (periodic 128^3, 400 steps, checkpoints every 20);
 the STREAM-copy bandwidth of the GPU; and the FP64 CPU oracle timed on this
 host's cores on a bounded sample (the 128^3 crop of the same geometry).
@@ -49,8 +51,9 @@ def parse():
                     help="timed steps of the other legs (at most --steps)")
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic porous box")
     ap.add_argument("--only", default="",
-                    help="comma list of legs: f32,f16,bf16,f64,f32x,adjoint,copy,cpu,large,cavity,"
-                         "split,incomp")
+                    help="comma list of legs: f32,f16,bf16,f64,f32x (single steps), f32x2,f16x2,"
+                         "bf16x2,f64x2 (two steps per pass),adjoint,copy,cpu,large,cavity,split,"
+                         "incomp")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--sweep", action="store_true",
                     help="domain-size sweep instead of the headline run: periodic all-fluid cubes "
@@ -542,6 +545,7 @@ KERNELS = {  # record key -> (kernel name, box edge, bytes per fluid update, por
     "f32x": ("void lbm::k_step<4, 1, true, false, 1>", 512, 152, True, 1),
     "f32x2": ("void lbm::k_step2<0, 1, true, false>", 512, 152, True, 2),
     "f16x2": ("void lbm::k_step2<1, 1, true, false>", 512, 76, True, 2),
+    "f64x2": ("void lbm::k_step2<3, 1, true, false>", 512, 304, True, 2),
     "adjoint": ("void lbm::k_adj<false, false, false>", 256, 228, False, 1),  # periodic, no flags
 }
 
@@ -776,6 +780,7 @@ ROOFLINE_KERNELS = {  # leg -> kernel named in the roofline object
     "f32x": "k_step<F32X, static walls, force, Qian>",
     "f16x2": "k_step2<F16, static walls, force, Qian> (two steps per launch)",
     "bf16x2": "k_step2<BF16, static walls, force, Qian> (two steps per launch)",
+    "f64x2": "k_step2<F64, static walls, force, Qian> (two steps per launch)",
 }
 
 
@@ -795,7 +800,7 @@ def roofline_of(key, leg):
     if spl == 2:
         out["note"] = ("algorithmic bytes of two single-step updates (the intermediate level stays "
                        "in LDS, so the kernel's HBM traffic is below them); the pass is bound by "
-                       "vector-instruction issue")
+                       "latency and instruction issue, not by HBM")
     return out
 
 
@@ -823,7 +828,7 @@ def main():
         return sweep(torch)
 
     legs = set(args.only.split(",")) if args.only else {"f32", "f16", "bf16", "f64", "f32x",
-                                                        "f32x2", "f16x2", "bf16x2",
+                                                        "f32x2", "f16x2", "bf16x2", "f64x2",
                                                         "adjoint", "copy", "cpu", "large", "cavity",
                                                         "split", "incomp"}
     n = args.n
@@ -864,12 +869,13 @@ def main():
         del fluid, rho32, u32
     fields.clear()
     torch.cuda.empty_cache()
-    if legs & {"f32x2", "f16x2", "bf16x2"}:
+    if legs & {"f32x2", "f16x2", "bf16x2", "f64x2"}:
         # the same workload with pairs of steps fused into one temporally blocked pass
-        for st, s in (("f32", 0), ("f16", 12), ("bf16", 0)):
+        for st, s in (("f32", 0), ("f16", 12), ("bf16", 0), ("f64", 0)):
             if f"{st}x2" in legs:
                 log(f"forward {st}, two steps per pass")
-                res[f"{st}x2"] = forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st, args.steps,
+                res[f"{st}x2"] = forward_leg(torch, LBM, flags_t, n_cells, n_fluid, st,
+                                             aux if st == "f64" else args.steps,
                                              args.warmup, s, steps_per_pass=2,
                                              clocks=clocks if st == "f32" else None)
                 log(f"  {res[f'{st}x2']['mlups']:.0f} MLUPS, {res[f'{st}x2']['alg_gbs']:.0f} GB/s "
@@ -969,7 +975,7 @@ def main():
         line["cavity"] = res["cavity"]
     if "split" in res:
         line["split_obstacle_kernel"] = res["split"]
-    for st in ("f16", "bf16"):
+    for st in ("f16", "bf16", "f64"):
         if f"{st}x2" in res:
             line[f"{st}_two_steps_per_pass"] = dict(res[f"{st}x2"],
                                                     roofline=roofline_of(f"{st}x2", res[f"{st}x2"]))
