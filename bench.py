@@ -374,6 +374,15 @@ def adjoint_leg(torch, n=128, steps=400, k=20):
     u0.grad = None
     g.grad = None
     tf, tb = run()
+    # the same forward sweep in fused pairs of steps (the same states, so the
+    # same backward)
+    with torch.no_grad():
+        rollout(u0.detach(), g.detach(), steps=steps, tau=0.6, checkpoint_every=k, steps_per_pass=2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rollout(u0.detach(), g.detach(), steps=steps, tau=0.6, checkpoint_every=k, steps_per_pass=2)
+        torch.cuda.synchronize()
+        tf2 = time.perf_counter() - t0
     # pure kernel times at the same size: forward step vs adjoint step
     sim = LBM((n, n, n), 0.6, (1e-6, 0, 0), "f32", u0=u0.detach())
     ms_fwd = timed_steps(sim, torch, 200, 20)
@@ -396,6 +405,7 @@ def adjoint_leg(torch, n=128, steps=400, k=20):
     out = {
         "workload": f"periodic {n}^3 FP32, tau 0.6, {steps} steps, checkpoints every {k}",
         "forward_s": tf, "backward_s": tb, "bwd_over_fwd": tb / tf,
+        "forward_s_two_steps_per_pass": tf2, "bwd_over_fwd_two_steps_per_pass": tb / tf2,
         "fwd_step_ms": ms_fwd, "adj_step_ms": ms_adj, "adj_kernel_over_fwd_kernel": ms_adj / ms_fwd,
         "adj_kernel_alg_gbs": 228 * cells / ms_adj / 1e6,
         "grad_finite": bool(torch.isfinite(u0.grad).all().item() and torch.isfinite(g.grad).all().item()),

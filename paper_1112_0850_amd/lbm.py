@@ -199,15 +199,14 @@ class _Rollout(torch.autograd.Function):
     checkpoints every k steps and recomputation inside each segment."""
 
     @staticmethod
-    def forward(ctx, u0, g, steps, tau, flags, k, wall_u, equilibrium):
+    def forward(ctx, u0, g, steps, tau, flags, k, wall_u, equilibrium, steps_per_pass):
         force = [float(v) for v in g.detach().double().cpu().tolist()]
         sim = LBM(u0.shape[1:], tau, force, "f32", flags=flags, u0=u0.detach(), device=u0.device,
-                  wall_u=wall_u, equilibrium=equilibrium)
+                  wall_u=wall_u, equilibrium=equilibrium, steps_per_pass=steps_per_pass)
         ckpts = []
-        for t in range(steps):
-            if t % k == 0:
-                ckpts.append(sim.save())
-            sim.step(1)
+        for t in range(0, steps, k):  # a checkpoint at the start of every segment of k steps
+            ckpts.append(sim.save())
+            sim.step(min(k, steps - t))
         rho, u = sim.macroscopics()
         ctx.sim, ctx.ckpts, ctx.steps, ctx.k = sim, ckpts, steps, k
         ctx.g_meta = (g.dtype, g.device)
@@ -246,15 +245,18 @@ class _Rollout(torch.autograd.Function):
         dF = torch.empty(3, dtype=torch.float64, device=dev)
         A.lbm_adjoint_finish_dF(sim.ctx, _ptr(partials), _ptr(dF))
         gdt, gdev = ctx.g_meta
-        return du0, dF.to(device=gdev, dtype=gdt), None, None, None, None, None, None
+        return du0, dF.to(device=gdev, dtype=gdt), None, None, None, None, None, None, None
 
 
 def rollout(u0, g, *, steps, tau, flags=None, checkpoint_every=20, wall_u=(0.0, 0.0, 0.0),
-            equilibrium="qian"):
+            equilibrium="qian", steps_per_pass=0):
     """Differentiable D3Q19 BGK rollout (FP32 storage): returns (rho_T, u_T)
     with gradients for the initial velocity ``u0`` [3, nz, ny, nx] and the
     body-force density ``g`` [3].  Moving walls and the incompressible
-    equilibrium are supported (no gradient for the wall velocity)."""
+    equilibrium are supported (no gradient for the wall velocity).
+    ``steps_per_pass=2`` runs the forward sweep in fused pairs of steps (the
+    same states bit for bit, so the same gradients); the reverse sweep
+    recomputes single states between checkpoints either way."""
     if u0.dim() != 4 or u0.shape[0] != 3:
         raise ValueError("u0 must be [3, nz, ny, nx]")
     if g.numel() != 3:
@@ -262,4 +264,4 @@ def rollout(u0, g, *, steps, tau, flags=None, checkpoint_every=20, wall_u=(0.0, 
     if steps < 1 or checkpoint_every < 1:
         raise ValueError("steps and checkpoint_every must be >= 1")
     return _Rollout.apply(u0, g.reshape(3), int(steps), float(tau), flags, int(checkpoint_every),
-                          tuple(float(v) for v in wall_u), equilibrium)
+                          tuple(float(v) for v in wall_u), equilibrium, int(steps_per_pass))

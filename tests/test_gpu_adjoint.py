@@ -99,10 +99,11 @@ def test_adjoint_seed_and_init_kernels_vs_oracle(case):
     assert rel_linf(du0.double().cpu().numpy(), ref) <= 1e-6
 
 
-def _gpu_grad(u0, target, F, flags, tau, steps, k):
+def _gpu_grad(u0, target, F, flags, tau, steps, k, steps_per_pass=0):
     u0t = torch.from_numpy(u0).float().cuda().requires_grad_(True)
     g = torch.tensor(F, dtype=torch.float64, requires_grad=True)
-    rho, u = rollout(u0t, g, steps=steps, tau=tau, flags=flags, checkpoint_every=k)
+    rho, u = rollout(u0t, g, steps=steps, tau=tau, flags=flags, checkpoint_every=k,
+                     steps_per_pass=steps_per_pass)
     fl = torch.ones(u0.shape[1:], dtype=torch.bool, device="cuda") if flags is None else \
         torch.from_numpy((flags & 1) == 0).cuda()
     tt = torch.from_numpy(target).float().cuda()
@@ -203,4 +204,22 @@ def test_checkpoint_spacing_gives_identical_gradients():
     ref = _gpu_grad(u0, target, F, flags, tau, steps, 1)
     for k in (7, 20, 40):
         got = _gpu_grad(u0, target, F, flags, tau, steps, k)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), k
+
+
+def test_forward_in_fused_pairs_gives_identical_gradients():
+    """The forward sweep in fused pairs of steps (even and odd segment
+    lengths: k = 7 ends every segment with a single step) reaches the same
+    states bit for bit, so the gradients and the loss are identical."""
+    n, tau, steps = 32, 0.6, 41
+    say("rollout forward in fused pairs, k = 7 / 20")
+    flags = I.random_flags((n, n, n), 4, solid_fraction=0.05, noforce_fraction=0.1)
+    u0 = _f32(I.smooth_field(n, 8, amplitude=0.02, modes=4))
+    u0[:, flags & 1 == 1] = 0
+    target = _f32(I.smooth_field(n, 9, amplitude=0.02, modes=4))
+    F = np.array([1e-5, -2e-6, 0])
+    for k in (7, 20):
+        ref = _gpu_grad(u0, target, F, flags, tau, steps, k)
+        got = _gpu_grad(u0, target, F, flags, tau, steps, k, steps_per_pass=2)
+        assert got[2] == ref[2], k
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), k
