@@ -129,7 +129,7 @@ def test_two_step_pass_porous_parity_vs_oracle():
     assert e_rho <= 1e-5 and e_u <= 1e-5
 
 
-@pytest.mark.parametrize("storage,s", [("f32", 0), ("f16", 12)])
+@pytest.mark.parametrize("storage,s", [("f32", 0), ("f16", 12), ("bf16", 0), ("f64", 0), ("f32x", 0)])
 def test_two_step_pass_at_full_size(storage, s):
     """The benchmark's 512^3 porous box (10% spheres, seed 12345, tau 0.55,
     g_x 1e-6) from a sheared start: 6 steps in fused pairs == 6 single steps,
@@ -149,13 +149,14 @@ def test_two_step_pass_at_full_size(storage, s):
     torch.cuda.empty_cache()
 
 
-def test_two_step_pass_cavity_at_full_size():
+@pytest.mark.parametrize("storage,s", [("f32", 0), ("f16", 10)])
+def test_two_step_pass_cavity_at_full_size(storage, s):
     n = 512
-    say(f"two-step pass at {n}^3 lid-driven cavity, f32")
+    say(f"two-step pass at {n}^3 lid-driven cavity, {storage}")
     flags = I.cavity_flags((n, n, n))
-    kw = dict(flags=flags, wall_u=(0.05, 0, 0))
-    one = LBM((n, n, n), 0.55, (0, 0, 0), "f32", **kw).step(4)
-    two = LBM((n, n, n), 0.55, (0, 0, 0), "f32", steps_per_pass=2, **kw).step(4)
+    kw = dict(flags=flags, wall_u=(0.05, 0, 0), f16_scale_log2=s)
+    one = LBM((n, n, n), 0.55, (0, 0, 0), storage, **kw).step(4)
+    two = LBM((n, n, n), 0.55, (0, 0, 0), storage, steps_per_pass=2, **kw).step(4)
     torch.cuda.synchronize()
     assert _same(one, two)
     del one, two
