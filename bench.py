@@ -553,9 +553,9 @@ KERNELS = {  # record key -> (kernel name, box edge, bytes per fluid update, por
     "bf16": ("void lbm::k_step<2, 1, true, false, 4>", 512, 76, True, 1),
     "f64": ("void lbm::k_step<3, 1, true, false, 1>", 512, 304, True, 1),
     "f32x": ("void lbm::k_step<4, 1, true, false, 1>", 512, 152, True, 1),
-    "f32x2": ("void lbm::k_step2<0, 1, true, false>", 512, 152, True, 2),
-    "f16x2": ("void lbm::k_step2<1, 1, true, false>", 512, 76, True, 2),
-    "f64x2": ("void lbm::k_step2<3, 1, true, false>", 512, 304, True, 2),
+    "f32x2": ("void lbm::k_step2<0, 1, true, false, false>", 512, 152, True, 2),
+    "f16x2": ("void lbm::k_step2<1, 1, true, false, false>", 512, 76, True, 2),
+    "f64x2": ("void lbm::k_step2<3, 1, true, false, false>", 512, 304, True, 2),
     "adjoint": ("void lbm::k_adj<false, false, false>", 256, 228, False, 1),  # periodic, no flags
 }
 

@@ -221,6 +221,16 @@ lbm_status lbm_step(lbm_ctx* ctx, int32_t n);
  * are rewritten; its fluid values are not.  Errors: LBM_E_ARG, LBM_E_HIP. */
 lbm_status lbm_step_from(lbm_ctx* ctx, const void* src, void* dst);
 
+/* Two steps from an arbitrary grid `src` (state f*(t)) in one fused pass
+ * (the steps of lbm_step_from twice, bit for bit): `mid` receives f*(t+1)
+ * and `dst` f*(t+2); the context's own grids and time are untouched.  src,
+ * mid and dst must be distinct, 256-byte aligned grids of the context's
+ * layout.  Used by the adjoint's recomputation of the forward states
+ * between checkpoints (one read of f* per two states).  Errors: LBM_E_ARG,
+ * LBM_E_UNSUPPORTED (storage other than LBM_F32, or obstacle_kernel = 1),
+ * LBM_E_HIP. */
+lbm_status lbm_step2_from(lbm_ctx* ctx, const void* src, void* mid, void* dst);
+
 /* Macroscopic fields of the current time level t from the stored f*(t):
  * the moments of Sec. 2 (density and momentum as the zeroth and first
  * moments of the populations, the quantities of the collision step),

@@ -45,6 +45,7 @@ _SIGNATURES = {
     "lbm_init": (_st, [C.POINTER(_vp), C.POINTER(lbm_params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "lbm_step": (_st, [_vp, C.c_int32]),
     "lbm_step_from": (_st, [_vp, _vp, _vp]),
+    "lbm_step2_from": (_st, [_vp, _vp, _vp, _vp]),
     "lbm_macroscopics": (_st, [_vp, _vp, _vp]),
     "lbm_macroscopics_f64": (_st, [_vp, _vp, _vp]),
     "lbm_reduce": (_st, [_vp, _vp]),
@@ -155,6 +156,10 @@ def lbm_step(ctx, n):
 
 def lbm_step_from(ctx, src, dst):
     check(lib().lbm_step_from(ctx, src, dst))
+
+
+def lbm_step2_from(ctx, src, mid, dst):
+    check(lib().lbm_step2_from(ctx, src, mid, dst))
 
 
 def lbm_macroscopics(ctx, rho, u):

@@ -422,6 +422,22 @@ lbm_status lbm_step_from(lbm_ctx* c, const void* src, void* dst) {
   return launch_steps(c, src, dst);
 }
 
+lbm_status lbm_step2_from(lbm_ctx* c, const void* src, void* mid, void* dst) {
+  lbm_status st = check_ctx(c);
+  if (st != LBM_OK) return st;
+  if (!src || !mid || !dst) return fail(LBM_E_ARG, "src, mid and dst must not be NULL");
+  if (src == mid || src == dst || mid == dst) return fail(LBM_E_ARG, "src, mid and dst must differ");
+  if (!aligned256(src) || !aligned256(mid) || !aligned256(dst))
+    return fail(LBM_E_ARG, "src/mid/dst must be 256-byte aligned");
+  if (c->p.storage != LBM_F32)
+    return fail(LBM_E_UNSUPPORTED, "lbm_step2_from needs FP32 storage");
+  if (c->p.obstacle_kernel)
+    return fail(LBM_E_UNSUPPORTED, "lbm_step2_from is not available with obstacle_kernel = 1");
+  hipError_t e = lbm::launch_step2_mid(c->p.storage, c->flags != nullptr, c->force, c->geo, c->ph,
+                                       src, mid, dst, c->flags, c->stream);
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "two-step launch");
+}
+
 static lbm_status macro_any(lbm_ctx* c, void* rho, void* u, bool f64) {
   lbm_status st = check_ctx(c);
   if (st != LBM_OK) return st;

@@ -57,6 +57,11 @@ hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const
 // not for the split design).
 hipError_t launch_step2(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
                         const void* src, void* dst, const uint8_t* flags, hipStream_t s);
+// The same two steps storing the intermediate level too: mid = f*(t+1)
+// (FP32 storage only: hipErrorInvalidValue otherwise).
+hipError_t launch_step2_mid(int storage, bool solids, bool force, const Geo& g,
+                            const PhysParams& ph, const void* src, void* mid, void* dst,
+                            const uint8_t* flags, hipStream_t s);
 hipError_t launch_obstacle(int storage, const Geo& g, const PhysParams& ph, void* grid,
                            const uint8_t* flags, hipStream_t s);
 hipError_t launch_macro(int storage, bool out_f64, const Geo& g, const PhysParams& ph,

@@ -646,10 +646,14 @@ __device__ __forceinline__ void store_nt_at(uint64_t base, uint32_t off, T v) {
   __builtin_nontemporal_store(v, reinterpret_cast<__attribute__((address_space(1))) T*>(base + off));
 }
 
-template <int K, int WALLS, bool FORCE, bool INC>
+// MID: the intermediate level f*(t+1) is stored as well, into `mid` (each
+// cell by the block whose tile and chunk own it), for callers that need every
+// state -- the adjoint's recomputation between checkpoints.
+template <int K, int WALLS, bool FORCE, bool INC, bool MID>
 __global__ __launch_bounds__(64 * (tb2_rows<K>() + 3)) void k_step2(
-    const typename Storage<K>::T* __restrict__ src, typename Storage<K>::T* __restrict__ dst,
-    const uint8_t* __restrict__ flags, Geo2 g, StepK<typename Storage<K>::C> k) {
+    const typename Storage<K>::T* __restrict__ src, typename Storage<K>::T* __restrict__ mid,
+    typename Storage<K>::T* __restrict__ dst, const uint8_t* __restrict__ flags, Geo2 g,
+    StepK<typename Storage<K>::C> k) {
   using C = typename Storage<K>::C;
   using T = typename Storage<K>::T;
   constexpr int TY = tb2_rows<K>(), TX = 64, EX = TX + 2, EY = TY + 2;
@@ -773,6 +777,16 @@ __global__ __launch_bounds__(64 * (tb2_rows<K>() + 3)) void k_step2(
         const int tx = ex + D3Q19::cx[i], ty = ey + D3Q19::cy[i];
         if (tx >= -1 && tx <= TX && ty >= -1 && ty <= TY)
           ring_at(tb2_nslot(i) == 3 ? w3 : w2, i, D3Q19::cy[i], D3Q19::cx[i]) = v;
+      }
+    }
+    if constexpr (MID) {
+      if (out_ok && p >= z0 && p < zend) {
+        uint64_t base = uniform_opaque(reinterpret_cast<uint64_t>(mid));
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          store_nt_at<T>(base, ownb, cur[i]);
+          if (i + 1 < Q) base = uniform_opaque(base + pb);
+        }
       }
     }
     if (p < zend) issue(p + 1);
@@ -1521,16 +1535,16 @@ static Geo2 make_geo2(const Geo& g, int rows) {
   return h;
 }
 
-template <int K, int WALLS, bool FORCE, bool INC>
+template <int K, int WALLS, bool FORCE, bool INC, bool MID = false>
 static void step2_t(const Geo& g, const PhysParams& ph, const void* src, void* dst,
-                    const uint8_t* flags, hipStream_t s) {
+                    const uint8_t* flags, hipStream_t s, void* mid = nullptr) {
   using S = Storage<K>;
   constexpr int rows = tb2_rows<K>();
   const Geo2 h = make_geo2(g, rows);
-  hipLaunchKernelGGL((k_step2<K, WALLS, FORCE, INC>), dim3(h.nblocks), dim3(64 * (rows + 3)), 0,
-                     s, reinterpret_cast<const typename S::T*>(src),
-                     reinterpret_cast<typename S::T*>(dst), flags, h,
-                     make_stepk<typename S::C>(ph));
+  hipLaunchKernelGGL((k_step2<K, WALLS, FORCE, INC, MID>), dim3(h.nblocks), dim3(64 * (rows + 3)),
+                     0, s, reinterpret_cast<const typename S::T*>(src),
+                     reinterpret_cast<typename S::T*>(mid), reinterpret_cast<typename S::T*>(dst),
+                     flags, h, make_stepk<typename S::C>(ph));
 }
 
 template <int K, int WALLS, bool INC>
@@ -1565,6 +1579,33 @@ hipError_t launch_step2(int storage, bool solids, bool force, const Geo& g, cons
     case ST_F32X: step2_k<ST_F32X>(solids, force, g, ph, src, dst, flags, s); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// Two fused steps that also store the intermediate level (FP32 storage, the
+// adjoint's storage): src = f*(t) -> mid = f*(t+1), dst = f*(t+2).
+template <int WALLS, bool INC>
+static void step2_mid_f(bool force, const Geo& g, const PhysParams& ph, const void* src, void* mid,
+                        void* dst, const uint8_t* flags, hipStream_t s) {
+  if (force) step2_t<ST_F32, WALLS, true, INC, true>(g, ph, src, dst, flags, s, mid);
+  else step2_t<ST_F32, WALLS, false, INC, true>(g, ph, src, dst, flags, s, mid);
+}
+
+template <bool INC>
+static void step2_mid_w(bool solids, bool force, const Geo& g, const PhysParams& ph,
+                        const void* src, void* mid, void* dst, const uint8_t* flags,
+                        hipStream_t s) {
+  if (!solids) step2_mid_f<0, INC>(force, g, ph, src, mid, dst, flags, s);
+  else if (!ph.moving) step2_mid_f<1, INC>(force, g, ph, src, mid, dst, flags, s);
+  else step2_mid_f<2, INC>(force, g, ph, src, mid, dst, flags, s);
+}
+
+hipError_t launch_step2_mid(int storage, bool solids, bool force, const Geo& g,
+                            const PhysParams& ph, const void* src, void* mid, void* dst,
+                            const uint8_t* flags, hipStream_t s) {
+  if (storage != ST_F32) return hipErrorInvalidValue;
+  if (ph.incomp) step2_mid_w<true>(solids, force, g, ph, src, mid, dst, flags, s);
+  else step2_mid_w<false>(solids, force, g, ph, src, mid, dst, flags, s);
   return hipGetLastError();
 }
 

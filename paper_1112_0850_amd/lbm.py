@@ -7,6 +7,7 @@ include/lbm.h.  Shapes are (nz, ny, nx); fields are [nz, ny, nx] and
 [3, nz, ny, nx]; populations [19, nz, ny, x_stride] in the interface order.
 """
 import ctypes
+import math
 
 import torch
 
@@ -119,6 +120,12 @@ class LBM:
     def step_from(self, src, dst):
         A.lbm_step_from(self.ctx, _ptr(_aligned(src, "src")), _ptr(_aligned(dst, "dst")))
 
+    def step2_from(self, src, mid, dst):
+        """Two steps from ``src`` in one fused pass: ``mid`` gets the first
+        state, ``dst`` the second (FP32 storage)."""
+        A.lbm_step2_from(self.ctx, _ptr(_aligned(src, "src")), _ptr(_aligned(mid, "mid")),
+                         _ptr(_aligned(dst, "dst")))
+
     def macroscopics(self, f64=False):
         dt = torch.float64 if f64 else torch.float32
         rho = torch.empty(self.shape, dtype=dt, device=self.device)
@@ -193,6 +200,12 @@ def copy_probe(dst, src, vec_per_thread=1, nontemporal=False, blocks=0, stream=N
                      blocks, ctypes.c_void_p(s.cuda_stream))
 
 
+# The reverse sweep recomputes two states per fused pass (lbm_step2_from)
+# from this many cells on: measured, the backward runs 3% faster at 256^3
+# and 6% slower at 128^3, where the pass has too few blocks to fill the GPU.
+FUSED_RECOMPUTE_MIN_CELLS = 1 << 24
+
+
 class _Rollout(torch.autograd.Function):
     """(rho_T, u_T) after `steps` updates from f*(0) = f^eq(1, u0) under the
     body force g; backward runs the hand-written adjoint kernels with forward
@@ -227,11 +240,18 @@ class _Rollout(torch.autograd.Function):
         gu = None if g_u is None else g_u.to(torch.float32).contiguous()
         cur = 0
         seg = [None] + [sim.new_grid() for _ in range(min(k, steps) - 1)]
+        fused = math.prod(sim.shape) >= FUSED_RECOMPUTE_MIN_CELLS
         for s in range(len(ckpts) - 1, -1, -1):
             t0, t1 = s * k, min(s * k + k, steps)
             seg[0] = ckpts[s]
-            for j in range(1, t1 - t0):
-                sim.step_from(seg[j - 1], seg[j])
+            j = 1
+            while j < t1 - t0:  # recompute the segment's states
+                if fused and j + 1 < t1 - t0:  # two states per pass
+                    sim.step2_from(seg[j - 1], seg[j], seg[j + 1])
+                    j += 2
+                else:
+                    sim.step_from(seg[j - 1], seg[j])
+                    j += 1
             for m in range(t1 - 1, t0 - 1, -1):  # f*(m) gives nu^{m+1}
                 if m == steps - 1:
                     A.lbm_adjoint_seed(sim.ctx, _ptr(seg[m - t0]), _ptr(gr), _ptr(gu),

@@ -146,6 +146,9 @@ def test_null_context_rejected():
     assert e.value.status == A.LBM_E_ARG
     with pytest.raises(A.LBMError):
         A.lbm_reduce(None, None)
+    with pytest.raises(A.LBMError) as e:
+        A.lbm_step2_from(None, ctypes.c_void_p(0x100), ctypes.c_void_p(0x200), ctypes.c_void_p(0x300))
+    assert e.value.status == A.LBM_E_ARG
     assert A.lbm_current(None) == -1 and A.lbm_time(None) == -1
     with pytest.raises(A.LBMError):
         A.lbm_stream_copy(ctypes.c_void_p(0x100), ctypes.c_void_p(0x200), 17, None)

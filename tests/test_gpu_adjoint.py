@@ -223,3 +223,22 @@ def test_forward_in_fused_pairs_gives_identical_gradients():
         got = _gpu_grad(u0, target, F, flags, tau, steps, k, steps_per_pass=2)
         assert got[2] == ref[2], k
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), k
+
+
+def test_fused_recomputation_gives_identical_gradients(monkeypatch):
+    """The reverse sweep's recomputation in fused pairs (lbm_step2_from,
+    used from 256^3 on) reaches the same states, so the same gradients: the
+    threshold lowered to force it on a small box, odd and even segments."""
+    from paper_1112_0850_amd import lbm as L
+    n, tau, steps = 24, 0.6, 23
+    flags = I.random_flags((n, n, n), 14, solid_fraction=0.08, noforce_fraction=0.1)
+    u0 = _f32(I.smooth_field(n, 15, amplitude=0.02, modes=3))
+    u0[:, flags & 1 == 1] = 0
+    target = _f32(I.smooth_field(n, 16, amplitude=0.02, modes=3))
+    F = np.array([2e-5, 0, -1e-5])
+    for k in (6, 9):
+        monkeypatch.setattr(L, "FUSED_RECOMPUTE_MIN_CELLS", 1 << 40)
+        ref = _gpu_grad(u0, target, F, flags, tau, steps, k)
+        monkeypatch.setattr(L, "FUSED_RECOMPUTE_MIN_CELLS", 0)
+        got = _gpu_grad(u0, target, F, flags, tau, steps, k)
+        assert got[2] == ref[2] and np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), k

@@ -11,6 +11,7 @@ import pytest
 import torch
 
 from oracle import oracle as O
+from paper_1112_0850_amd import _abi as A
 from paper_1112_0850_amd import inputs as I
 from paper_1112_0850_amd.lbm import LBM
 from tests.gpu_util import check_solids, rel_linf, say
@@ -239,3 +240,48 @@ def test_two_step_pass_at_maximum_size():
     _sampled_two_steps(sim, flags, [(z * n + y) * n + x for z, y, x in zyx], 0.55, (1e-6, 0, 0))
     del sim
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("case", ["porous", "moving_walls", "incompressible", "periodic_ragged"])
+def test_step2_from_stores_both_states(case):
+    """lbm_step2_from (the adjoint's recomputation): mid == one step_from,
+    dst == two, bit for bit, on arbitrary grids; the context's own grids and
+    time are untouched."""
+    shape = (21, 17, 70) if case == "periodic_ragged" else (12, 15, 66)
+    say("step2_from", case, shape)
+    kw = dict(u0=_u0(shape, 11))
+    if case in ("porous", "incompressible"):
+        kw["flags"] = I.random_flags(shape, 12, solid_fraction=0.2, noforce_fraction=0.1)
+    elif case == "moving_walls":
+        kw["flags"] = (I.random_flags(shape, 13, solid_fraction=0.1, noforce_fraction=0.1)
+                       | I.cavity_flags(shape))
+        kw["wall_u"] = (0.03, 0.01, -0.02)
+    if "flags" in kw:
+        kw["u0"][:, torch.from_numpy(kw["flags"] & 1 == 1)] = 0
+    eq = "incompressible" if case == "incompressible" else "qian"
+    sim = LBM(shape, 0.62, (3e-5, -1e-5, 2e-5), "f32", equilibrium=eq, **kw).step(3)
+    src = sim.grids[sim.current].clone()
+    t0, cur0 = sim.t, sim.current
+    a1, a2, m, d = (sim.new_grid() for _ in range(4))
+    for g_ in (a1, a2, m, d):
+        g_.fill_(7)  # the padding stays as it was: compare the written cells only
+    sim.step_from(src, a1)
+    sim.step_from(a1, a2)
+    sim.step2_from(src, m, d)
+    torch.cuda.synchronize()
+    assert sim.t == t0 and sim.current == cur0
+    assert torch.equal(sim.grids[sim.current], src)
+    assert torch.equal(m, a1) and torch.equal(d, a2)
+
+
+def test_step2_from_rejects_other_storage():
+    sim = LBM((8, 8, 64), 0.7, (0, 0, 0), "f16", f16_scale_log2=10)
+    a, b, c = sim.new_grid(), sim.new_grid(), sim.new_grid()
+    with pytest.raises(A.LBMError) as e:
+        sim.step2_from(a, b, c)
+    assert e.value.status == A.LBM_E_UNSUPPORTED
+    sim32 = LBM((8, 8, 64), 0.7, (0, 0, 0), "f32")
+    a = sim32.new_grid()
+    with pytest.raises(A.LBMError) as e:
+        sim32.step2_from(a, a, sim32.new_grid())
+    assert e.value.status == A.LBM_E_ARG
