@@ -127,6 +127,10 @@ enum { LBM_FLAG_SOLID = 1, LBM_FLAG_NOFORCE = 2, LBM_FLAG_MOVING = 4 };
 #define LBM_MARK_BF16_REST 0xFFD4u
 #define LBM_MARK_BF16_MOVING 0xFFD5u
 
+/* lbm_params.steps_per_pass value for the automatic choice between one and
+ * two steps per kernel pass. */
+#define LBM_STEPS_AUTO (-1)
+
 typedef struct {
   int32_t nx, ny, nz;     /* cells per axis, each >= 1 */
   int32_t storage;        /* lbm_storage */
@@ -153,7 +157,12 @@ typedef struct {
                              blocking along z, half the HBM traffic of two
                              passes), bit-identical to single steps; an odd
                              remainder is one single step.  Not with
-                             obstacle_kernel = 1 (LBM_E_UNSUPPORTED). */
+                             obstacle_kernel = 1 (LBM_E_UNSUPPORTED).
+                             LBM_STEPS_AUTO: pairs where the fused pass fills
+                             the GPU (at least 128 blocks of its tiles: from
+                             about 128^3 cells on), single steps elsewhere and
+                             with the split design -- the fastest schedule
+                             measured, the same bits either way. */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;

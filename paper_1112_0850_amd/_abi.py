@@ -14,6 +14,7 @@ LBM_OK, LBM_E_ARG, LBM_E_HIP, LBM_E_UNSUPPORTED, LBM_E_STATE = 0, -1, -2, -3, -4
 LBM_F32, LBM_F16, LBM_BF16, LBM_F64, LBM_F32X = 0, 1, 2, 3, 4
 LBM_FLAG_SOLID, LBM_FLAG_NOFORCE, LBM_FLAG_MOVING = 1, 2, 4
 LBM_EQ_QIAN, LBM_EQ_INCOMPRESSIBLE = 0, 1
+LBM_STEPS_AUTO = -1
 
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_E_ARG", -2: "LBM_E_HIP", -3: "LBM_E_UNSUPPORTED",
                 -4: "LBM_E_STATE"}
@@ -109,7 +110,7 @@ def params(shape, tau, force=(0.0, 0.0, 0.0), storage=LBM_F32, f16_scale_log2=0,
         p.wall_u[d] = float(wall_u[d])
     p.equilibrium = int(equilibrium)
     p.obstacle_kernel = int(obstacle_kernel)
-    p.steps_per_pass = int(steps_per_pass)
+    p.steps_per_pass = LBM_STEPS_AUTO if steps_per_pass == "auto" else int(steps_per_pass)
     return p
 
 

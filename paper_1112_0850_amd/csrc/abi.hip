@@ -95,8 +95,9 @@ lbm_status check_params(const lbm_params* p, Sizes* sz) {
     return fail(LBM_E_ARG, "unknown equilibrium %d", p->equilibrium);
   if (p->obstacle_kernel != 0 && p->obstacle_kernel != 1)
     return fail(LBM_E_ARG, "obstacle_kernel must be 0 or 1 (got %d)", p->obstacle_kernel);
-  if (p->steps_per_pass < 0 || p->steps_per_pass > 2)
-    return fail(LBM_E_ARG, "steps_per_pass must be 0, 1 or 2 (got %d)", p->steps_per_pass);
+  if (p->steps_per_pass < LBM_STEPS_AUTO || p->steps_per_pass > 2)
+    return fail(LBM_E_ARG, "steps_per_pass must be -1 (automatic), 0, 1 or 2 (got %d)",
+                p->steps_per_pass);
   if (p->steps_per_pass == 2 && p->obstacle_kernel == 1)
     return fail(LBM_E_UNSUPPORTED, "two steps per pass are not available with the obstacle kernel");
   if (p->storage == LBM_F16 && (p->f16_scale_log2 < -24 || p->f16_scale_log2 > 24))
@@ -215,9 +216,15 @@ lbm_status launch_steps(lbm_ctx* c, const void* src, void* dst) {
 // *done the number of steps enqueued (all n unless a launch failed).
 lbm_status enqueue_steps(lbm_ctx* c, int32_t n, int* cur, hipStream_t s, int32_t* done) {
   *done = 0;
+  // 2: always fused pairs; automatic: pairs where the fused pass fills the
+  // GPU, single steps elsewhere and with the split design (the same bits)
+  const bool pairs =
+      c->p.steps_per_pass == 2 ||
+      (c->p.steps_per_pass == LBM_STEPS_AUTO && c->p.obstacle_kernel == 0 &&
+       lbm::step2_blocks(c->p.storage, c->geo) >= lbm::kStep2MinBlocks);
   while (n > 0) {
     const int k = *cur;
-    if (c->p.steps_per_pass == 2 && n >= 2) {
+    if (pairs && n >= 2) {
       hipError_t e = lbm::launch_step2(c->p.storage, c->flags != nullptr, c->force, c->geo, c->ph,
                                        c->grid[k], c->grid[k ^ 1], c->flags, s);
       if (e != hipSuccess) return hip_fail(e, "two-step launch");

@@ -57,6 +57,12 @@ hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const
 // not for the split design).
 hipError_t launch_step2(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
                         const void* src, void* dst, const uint8_t* flags, hipStream_t s);
+// Blocks a two-step launch has on this grid (its tiles and z chunks).
+int step2_blocks(int storage, const Geo& g);
+// Fewer blocks than this leave most CUs idle: single steps are faster there
+// (measured on periodic cubes: 112 blocks at 100^3 ran 22.0k MLUPS FP32
+// against 27.5k for single steps, 160 at 128^3 40.9k against 34.2k).
+constexpr int kStep2MinBlocks = 128;
 // The same two steps storing the intermediate level too: mid = f*(t+1)
 // (FP32 storage only: hipErrorInvalidValue otherwise).
 hipError_t launch_step2_mid(int storage, bool solids, bool force, const Geo& g,

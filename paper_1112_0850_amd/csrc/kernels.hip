@@ -1569,6 +1569,17 @@ static void step2_k(bool solids, bool force, const Geo& g, const PhysParams& ph,
   else step2_w<K, false>(solids, force, g, ph, src, dst, flags, s);
 }
 
+int step2_blocks(int storage, const Geo& g) {
+  switch (storage) {
+    case ST_F32: return make_geo2(g, tb2_rows<ST_F32>()).nblocks;
+    case ST_F16: return make_geo2(g, tb2_rows<ST_F16>()).nblocks;
+    case ST_BF16: return make_geo2(g, tb2_rows<ST_BF16>()).nblocks;
+    case ST_F64: return make_geo2(g, tb2_rows<ST_F64>()).nblocks;
+    case ST_F32X: return make_geo2(g, tb2_rows<ST_F32X>()).nblocks;
+    default: return 0;
+  }
+}
+
 hipError_t launch_step2(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
                         const void* src, void* dst, const uint8_t* flags, hipStream_t s) {
   switch (storage) {

@@ -50,7 +50,9 @@ class LBM:
     ``obstacle_kernel=1`` selects the split design (a separate bounce-back
     kernel before each step) instead of the fused solid markers;
     ``steps_per_pass=2`` runs pairs of steps as one temporally blocked pass
-    (same results, bit for bit)."""
+    (same results, bit for bit); ``steps_per_pass="auto"`` does so where the
+    pass fills the GPU (from about 128^3 cells on) and runs single steps
+    elsewhere."""
 
     def __init__(self, shape, tau, force=(0.0, 0.0, 0.0), storage="f32", flags=None, u0=None,
                  rho0=None, f16_scale_log2=0, x_align=0, device="cuda", wall_u=(0.0, 0.0, 0.0),

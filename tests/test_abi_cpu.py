@@ -205,8 +205,12 @@ def test_copy_probe_argument_errors():
 
 
 def test_steps_per_pass_option():
-    for v in (0, 1, 2):
+    for v in (0, 1, 2, -1, "auto"):
         A.lbm_query(A.params((4, 4, 4), 0.6, steps_per_pass=v))
+    A.lbm_query(A.params((4, 4, 4), 0.6, steps_per_pass="auto", obstacle_kernel=1))
+    with pytest.raises(A.LBMError) as e:
+        A.lbm_query(A.params((4, 4, 4), 0.6, steps_per_pass=-2))
+    assert e.value.status == A.LBM_E_ARG
     with pytest.raises(A.LBMError) as e:
         A.lbm_query(A.params((4, 4, 4), 0.6, steps_per_pass=3))
     assert e.value.status == A.LBM_E_ARG and "steps_per_pass" in str(e.value)

@@ -285,3 +285,21 @@ def test_step2_from_rejects_other_storage():
     with pytest.raises(A.LBMError) as e:
         sim32.step2_from(a, a, sim32.new_grid())
     assert e.value.status == A.LBM_E_ARG
+
+
+@pytest.mark.parametrize("storage,n", [("f32", 48), ("f32", 160), ("f16", 160), ("f64", 96)])
+def test_automatic_steps_per_pass(storage, n):
+    """steps_per_pass = "auto" (LBM_STEPS_AUTO): fused pairs where the pass
+    fills the GPU, single steps on small grids -- the same bits as single
+    steps either way (48^3 falls back; 160^3 and the FP64 96^3 fuse)."""
+    shape = (n, n, n)
+    say("automatic steps per pass", storage, shape)
+    flags = I.random_flags(shape, 17, solid_fraction=0.1, noforce_fraction=0.05)
+    u0 = _u0(shape, 18)
+    u0[:, torch.from_numpy(flags & 1 == 1)] = 0
+    s = 10 if storage == "f16" else 0
+    kw = dict(flags=flags, u0=u0, f16_scale_log2=s)
+    one = LBM(shape, 0.6, (1e-5, 0, 0), storage, **kw).step(7)
+    auto = LBM(shape, 0.6, (1e-5, 0, 0), storage, steps_per_pass="auto", **kw).step(7)
+    torch.cuda.synchronize()
+    assert _same(one, auto)
