@@ -581,9 +581,13 @@ def launch_threads(name, n):
 
 def box_of(name, grid):
     """The box edge of a launch from its grid size, trying the bench's own
-    sizes first (the two-step kernel's launches at 256^3 and 512^3 have the
-    same size: 1280 blocks)."""
-    return next((n for n in (512, 768, 640, 256, 128) if launch_threads(name, n) == grid), None)
+    sizes first: the two-step kernel's launches at 256^3 and 512^3 have the
+    same size (1280 blocks), and the bench runs it at 512^3 (and 768^3) on
+    the porous box and at 256^3 (and 128^3) on the adjoint's periodic box,
+    without solids (walls = 0)."""
+    periodic2 = name.startswith("void lbm::k_step2<") and name.split("<")[1].split(",")[1].strip() == "0"
+    order = (256, 128, 512, 768, 640) if periodic2 else (512, 768, 640, 256, 128)
+    return next((n for n in order if launch_threads(name, n) == grid), None)
 
 
 def profile_summary(trace_dir, fetch_dir, write_dir, n=512):

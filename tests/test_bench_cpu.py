@@ -104,6 +104,8 @@ def test_trace_summary_two_steps_per_launch(tmp_path, capsys):
     k2 = "void lbm::k_step2<0, 1, true, false, false>"
     g = b.launch_threads(k2, 512)
     assert b.box_of(k2, g) == 512
+    kp = "void lbm::k_step2<0, 0, true, false, true>"  # periodic: the adjoint's 256^3 box
+    assert b.launch_threads(kp, 256) == g and b.box_of(kp, g) == 256
     cols = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X"]
     lines, t = [",".join(cols)], 0
     for k in range(5):  # 1 warm-up launch of 9 us, then 4 timed launches of 6 us
