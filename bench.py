@@ -553,9 +553,9 @@ KERNELS = {  # record key -> (kernel name, box edge, bytes per fluid update, por
     "bf16": ("void lbm::k_step<2, 1, true, false, 4>", 512, 76, True, 1),
     "f64": ("void lbm::k_step<3, 1, true, false, 1>", 512, 304, True, 1),
     "f32x": ("void lbm::k_step<4, 1, true, false, 1>", 512, 152, True, 1),
-    "f32x2": ("void lbm::k_step2<0, 1, true, false, false>", 512, 152, True, 2),
-    "f16x2": ("void lbm::k_step2<1, 1, true, false, false>", 512, 76, True, 2),
-    "f64x2": ("void lbm::k_step2<3, 1, true, false, false>", 512, 304, True, 2),
+    "f32x2": ("void lbm::k_step2<0, 4, true, false, false>", 512, 152, True, 2),
+    "f16x2": ("void lbm::k_step2<1, 4, true, false, false>", 512, 76, True, 2),
+    "f64x2": ("void lbm::k_step2<3, 4, true, false, false>", 512, 304, True, 2),
     "adjoint": ("void lbm::k_adj<false, false, false>", 256, 228, False, 1),  # periodic, no flags
 }
 
@@ -787,14 +787,14 @@ def trace_summary(trace_dir, bench_json):
 
 ROOFLINE_KERNELS = {  # leg -> kernel named in the roofline object
     "f32": "k_step<F32, static walls, force, Qian>",
-    "f32x2": "k_step2<F32, static walls, force, Qian> (two steps per launch)",
+    "f32x2": "k_step2<F32, static walls (link mask), force, Qian> (two steps per launch)",
     "f16": "k_step<F16, static walls, force, Qian>",
     "bf16": "k_step<BF16, static walls, force, Qian>",
     "f64": "k_step<F64, static walls, force, Qian>",
     "f32x": "k_step<F32X, static walls, force, Qian>",
-    "f16x2": "k_step2<F16, static walls, force, Qian> (two steps per launch)",
-    "bf16x2": "k_step2<BF16, static walls, force, Qian> (two steps per launch)",
-    "f64x2": "k_step2<F64, static walls, force, Qian> (two steps per launch)",
+    "f16x2": "k_step2<F16, static walls (link mask), force, Qian> (two steps per launch)",
+    "bf16x2": "k_step2<BF16, static walls (link mask), force, Qian> (two steps per launch)",
+    "f64x2": "k_step2<F64, static walls (link mask), force, Qian> (two steps per launch)",
 }
 
 

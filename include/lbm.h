@@ -174,7 +174,10 @@ typedef struct lbm_ctx lbm_ctx;
  *   x_stride       padded x extent of a grid row, in cells;
  *   dir_stride     elements from one direction array to the next;
  *   grid_bytes     bytes of ONE population grid (two are needed);
- *   scratch_bytes  bytes of the reduction scratch passed to lbm_init;
+ *   scratch_bytes  bytes of the scratch passed to lbm_init: the reduction's
+ *                  partials and, when steps_per_pass is 2 or LBM_STEPS_AUTO
+ *                  (and two direction arrays span less than 4 GiB), 4 bytes
+ *                  per cell for the two-step pass's link mask;
  *   adj_partials_bytes  bytes of the dL/dF partial-sum buffer of the adjoint.
  * Errors: LBM_E_ARG for invalid parameters, LBM_E_UNSUPPORTED when one
  * direction's array would exceed 4 GiB - 1 or a grid exceeds 2^31 cells. */
@@ -204,7 +207,11 @@ lbm_status lbm_solid_markers(int32_t storage, uint64_t* rest, uint64_t* moving);
  * grids (padding included) is set to 0.
  *   grid_a, grid_b  two grids of grid_bytes (the two lattices of Sec. 2);
  *   flags           uint8 [nz][ny][nx] or NULL (all fluid);
- *   scratch         scratch_bytes of device memory for lbm_reduce;
+ *   scratch         scratch_bytes of device memory (lbm_reduce's partials;
+ *                   with flags and resting walls, the link mask that the
+ *                   two-step pass reads -- bit i of a cell set when its pull
+ *                   along c_i comes from a solid cell, built here from the
+ *                   flags);
  *   rho0            float [nz][ny][nx] or NULL (uniform 1);
  *   u0              float [3][nz][ny][nx] or NULL (rest);
  *   stream          a hipStream_t (NULL = default stream).
@@ -282,8 +289,9 @@ lbm_status lbm_set_current(lbm_ctx* ctx, int32_t parity, int64_t t);
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
 
 /* Rewrites the solid markers of the current grid (needed only after the
- * caller has written populations into a grid directly).  No-op without
- * flags.  Errors: LBM_E_ARG, LBM_E_HIP. */
+ * caller has written populations into a grid directly) and the link mask
+ * from the flags (needed after the caller has changed the flags).  No-op
+ * without flags.  Errors: LBM_E_ARG, LBM_E_HIP. */
 lbm_status lbm_refresh_solids(lbm_ctx* ctx);
 
 /* Device-to-device copy of the current grid to `dst` (lbm_save), or of `src`

@@ -77,6 +77,7 @@ struct Sizes {
   size_t grid_bytes;
   size_t scratch_bytes;
   size_t adj_bytes;
+  size_t mask_off;      // scratch byte offset of the two-step link mask (0: none)
 };
 
 lbm_status check_params(const lbm_params* p, Sizes* sz) {
@@ -120,6 +121,15 @@ lbm_status check_params(const lbm_params* p, Sizes* sz) {
     sz->dir = dir;
     sz->grid_bytes = (size_t(19) * dir * es + 255) / 256 * 256;
     sz->scratch_bytes = size_t(lbm::kReduceBlocks) * 5 * sizeof(double);
+    // the two-step pass's link mask follows the reduction partials, when two
+    // steps per pass may run and the pass can address a pair of direction
+    // arrays with 32-bit offsets
+    sz->mask_off = 0;
+    if ((p->steps_per_pass == 2 || p->steps_per_pass == LBM_STEPS_AUTO) &&
+        p->obstacle_kernel == 0 && 2 * dir * es < (uint64_t(1) << 32)) {
+      sz->mask_off = (sz->scratch_bytes + 255) / 256 * 256;
+      sz->scratch_bytes = sz->mask_off + (size_t(cells) * sizeof(uint32_t) + 255) / 256 * 256;
+    }
     sz->adj_bytes = size_t(g.nblocks) * 3 * sizeof(double);
   }
   return LBM_OK;
@@ -173,6 +183,7 @@ struct lbm_ctx {
   void* grid[2];
   const uint8_t* flags;
   double* scratch;
+  uint32_t* lmask;  // the two-step link mask in scratch (resting walls), or NULL
   hipStream_t stream;
   int32_t cur;
   int64_t t;
@@ -226,7 +237,7 @@ lbm_status enqueue_steps(lbm_ctx* c, int32_t n, int* cur, hipStream_t s, int32_t
     const int k = *cur;
     if (pairs && n >= 2) {
       hipError_t e = lbm::launch_step2(c->p.storage, c->flags != nullptr, c->force, c->geo, c->ph,
-                                       c->grid[k], c->grid[k ^ 1], c->flags, s);
+                                       c->grid[k], c->grid[k ^ 1], c->flags, c->lmask, s);
       if (e != hipSuccess) return hip_fail(e, "two-step launch");
       n -= 2;
       *done += 2;
@@ -373,6 +384,9 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* grid_a, void* grid
   c->grid[1] = grid_b;
   c->flags = flags;
   c->scratch = static_cast<double*>(scratch);
+  c->lmask = (flags && sz.mask_off && !c->ph.moving)
+                 ? reinterpret_cast<uint32_t*>(static_cast<char*>(scratch) + sz.mask_off)
+                 : nullptr;
   c->stream = static_cast<hipStream_t>(stream);
   c->cur = 0;
   c->t = 0;
@@ -386,6 +400,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* p, void* grid_a, void* grid
   if (e == hipSuccess) e = lbm::launch_fill_zero(grid_b, sz.grid_bytes, c->stream);
   if (e == hipSuccess)
     e = lbm::launch_init(p->storage, c->geo, c->ph, grid_a, flags, rho0, u0, c->stream);
+  if (e == hipSuccess && c->lmask) e = lbm::launch_link_mask(c->geo, flags, c->lmask, c->stream);
   if (e != hipSuccess) {
     delete c;
     return hip_fail(e, "initialisation launch");
@@ -441,7 +456,7 @@ lbm_status lbm_step2_from(lbm_ctx* c, const void* src, void* mid, void* dst) {
   if (c->p.obstacle_kernel)
     return fail(LBM_E_UNSUPPORTED, "lbm_step2_from is not available with obstacle_kernel = 1");
   hipError_t e = lbm::launch_step2_mid(c->p.storage, c->flags != nullptr, c->force, c->geo, c->ph,
-                                       src, mid, dst, c->flags, c->stream);
+                                       src, mid, dst, c->flags, c->lmask, c->stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "two-step launch");
 }
 
@@ -492,6 +507,7 @@ lbm_status lbm_refresh_solids(lbm_ctx* c) {
   if (!c->flags) return LBM_OK;
   hipError_t e =
       lbm::launch_mark_solids(c->p.storage, c->geo, c->ph, c->grid[c->cur], c->flags, c->stream);
+  if (e == hipSuccess && c->lmask) e = lbm::launch_link_mask(c->geo, c->flags, c->lmask, c->stream);
   return e == hipSuccess ? LBM_OK : hip_fail(e, "solid marker launch");
 }
 

@@ -55,8 +55,11 @@ hipError_t launch_step(int storage, bool solids, bool force, const Geo& g, const
                        const void* src, void* dst, const uint8_t* flags, hipStream_t s);
 // Two fused steps src = f*(t) -> dst = f*(t+2) (bit-identical to two launch_step calls;
 // not for the split design).
+// lmask: the link mask of launch_link_mask, or NULL (resting walls then use
+// the markers; moving walls always do).
 hipError_t launch_step2(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
-                        const void* src, void* dst, const uint8_t* flags, hipStream_t s);
+                        const void* src, void* dst, const uint8_t* flags, const uint32_t* lmask,
+                        hipStream_t s);
 // Blocks a two-step launch has on this grid (its tiles and z chunks).
 int step2_blocks(int storage, const Geo& g);
 // Fewer blocks than this leave most CUs idle: single steps are faster there
@@ -67,7 +70,11 @@ constexpr int kStep2MinBlocks = 128;
 // (FP32 storage only: hipErrorInvalidValue otherwise).
 hipError_t launch_step2_mid(int storage, bool solids, bool force, const Geo& g,
                             const PhysParams& ph, const void* src, void* mid, void* dst,
-                            const uint8_t* flags, hipStream_t s);
+                            const uint8_t* flags, const uint32_t* lmask, hipStream_t s);
+// The two-step kernel's link mask of every cell ([nz][ny][nx] uint32) from the
+// flags: bit i (1..18) for a blocked pull along c_i, bits 19 and 20 for the
+// cell's own SOLID and NOFORCE flags.
+hipError_t launch_link_mask(const Geo& g, const uint8_t* flags, uint32_t* mask, hipStream_t s);
 hipError_t launch_obstacle(int storage, const Geo& g, const PhysParams& ph, void* grid,
                            const uint8_t* flags, hipStream_t s);
 hipError_t launch_macro(int storage, bool out_f64, const Geo& g, const PhysParams& ph,

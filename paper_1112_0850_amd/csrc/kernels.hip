@@ -580,6 +580,31 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 // and one write of f*(t+2) -- about half of two single steps.
 // ---------------------------------------------------------------------------
 constexpr int kTB2Arrays = 36;  // LDS plane-arrays of [TY + 2][66]
+// link-mask bits besides the 18 links (bit i: the pull along c_i is blocked)
+constexpr uint32_t kLinkSolid = 1u << 19;
+constexpr uint32_t kLinkNoforce = 1u << 20;
+// All ones when bit i of m is set, else 0 (one sign-extending bit extract).
+__device__ __forceinline__ uint32_t link_sel(uint32_t m, int i) {
+  return uint32_t(__builtin_amdgcn_sbfe(int32_t(m), i, 1));
+}
+// sel ? a : b for sel all ones or 0: one bitfield select per dword (written
+// as an instruction: the compiler turns the bit operations back into a
+// compare and a conditional move, two instructions more).
+__device__ __forceinline__ uint32_t bfi32(uint32_t sel, uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(sel), "v"(a), "v"(b));
+  return r;
+}
+template <typename U>
+__device__ __forceinline__ U pick(uint32_t sel, U a, U b) {
+  if constexpr (sizeof(U) == 8) {
+    const uint32_t lo = bfi32(sel, uint32_t(a), uint32_t(b));
+    const uint32_t hi = bfi32(sel, uint32_t(a >> 32), uint32_t(b >> 32));
+    return (U(hi) << 32) | U(lo);
+  } else {
+    return U(bfi32(sel, uint32_t(a), uint32_t(b)));
+  }
+}
 constexpr int kTB2Chunk = 128;     // longest z chunk (planes per block)
 constexpr int kTB2MinChunk = 16;   // shortest z chunk
 constexpr int kTB2MinBlocks = 1280;  // five blocks per CU on 256 CUs
@@ -649,18 +674,29 @@ __device__ __forceinline__ void store_nt_at(uint64_t base, uint32_t off, T v) {
 // MID: the intermediate level f*(t+1) is stored as well, into `mid` (each
 // cell by the block whose tile and chunk own it), for callers that need every
 // state -- the adjoint's recomputation between checkpoints.
+//
+// WALLS = 4 here (resting walls, with the link mask; in the single-step
+// kernel 4 is the pull-copy probe): the solid neighbours of a
+// cell are known from its mask before its pulls are issued, so each pull
+// reads the population it needs -- the neighbour's f*_i, or for a blocked
+// link the own cell's f*_opp(i) -- in one load, with no marker test and no
+// dependent reload; step 2 takes the own cell's value for a blocked link by
+// its mask bit.  The same values reach the collision as with the markers,
+// so the results are the same bits.  The mask of a plane is loaded two
+// planes ahead.
 template <int K, int WALLS, bool FORCE, bool INC, bool MID>
 __global__ __launch_bounds__(64 * (tb2_rows<K>() + 3)) void k_step2(
     const typename Storage<K>::T* __restrict__ src, typename Storage<K>::T* __restrict__ mid,
-    typename Storage<K>::T* __restrict__ dst, const uint8_t* __restrict__ flags, Geo2 g,
-    StepK<typename Storage<K>::C> k) {
+    typename Storage<K>::T* __restrict__ dst, const uint8_t* __restrict__ flags,
+    const uint32_t* __restrict__ lmask, Geo2 g, StepK<typename Storage<K>::C> k) {
   using C = typename Storage<K>::C;
   using T = typename Storage<K>::T;
   constexpr int TY = tb2_rows<K>(), TX = 64, EX = TX + 2, EY = TY + 2;
   constexpr uint32_t SZ = sizeof(T);
   constexpr uint32_t PLB = uint32_t(EY * EX) * SZ;  // bytes of one LDS plane-array
   constexpr bool SOLIDS = WALLS >= 1;
-  constexpr bool MARKERS = WALLS >= 1;
+  constexpr bool LINKS = WALLS == 4;
+  constexpr bool MARKERS = SOLIDS && !LINKS;
   static_assert(sizeof(T) * kTB2Arrays * EY * EX <= 160 * 1024, "ring exceeds the LDS of a CU");
   __shared__ T ring[kTB2Arrays * EY * EX];
   // block -> tile: x tiles fastest, then y tiles, then z chunks; XCD k gets
@@ -709,29 +745,62 @@ __global__ __launch_bounds__(64 * (tb2_rows<K>() + 3)) void k_step2(
   // the next plane's pulls and flag byte, issued one iteration ahead
   T nv[Q];
   uint8_t nfl = 0;
+  // LINKS: the masks of planes p (m0, its pulls in flight), p + 1 (m1) and
+  // p + 2 (m2, loading)
+  uint32_t m0 = 0, m1 = 0, m2 = 0;
+  auto mask_at = [&](int p) { return lmask[uint32_t(wrap_mod(p, g.nz)) * fl_z + fl_yx]; };
   auto issue = [&](int p) {
     const int pz = wrap_mod(p, g.nz);
     const uint32_t zb_[3] = {uint32_t(pz + 1 == g.nz ? 0 : pz + 1) * zstride, uint32_t(pz) * zstride,
                              uint32_t(pz == 0 ? g.nz - 1 : pz - 1) * zstride};
     uint64_t base = uniform_opaque(src_u);
+    if constexpr (LINKS) {
+      // pairs (i, i + 1) = (c, -c) from the base of array i: a blocked i
+      // reads f*_{i+1} of the own cell (pb further), a blocked i + 1 reads
+      // f*_i of the own cell (offsets < 4 GiB: two arrays of at most 2 GiB,
+      // checked on the host)
+      const uint32_t m = m1;
+      const uint32_t own = zb_[1] + own_yx, pb32 = uint32_t(pb);
+      nv[0] = load_at<T>(base, own);
+      base = uniform_opaque(base + pb);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      nv[i] = load_at<T>(base, zb_[1 + D3Q19::cz[i]] + yb_[1 + D3Q19::cy[i]] +
-                                   xb_[1 + D3Q19::cx[i]]);
-      if (i + 1 < Q) base = uniform_opaque(base + pb);
+      for (int i = 1; i < Q; i += 2) {
+        const uint32_t ni = zb_[1 + D3Q19::cz[i]] + yb_[1 + D3Q19::cy[i]] + xb_[1 + D3Q19::cx[i]];
+        const uint32_t nj =
+            zb_[1 + D3Q19::cz[i + 1]] + yb_[1 + D3Q19::cy[i + 1]] + xb_[1 + D3Q19::cx[i + 1]];
+        nv[i] = load_at<T>(base, pick(link_sel(m, i), pb32 + own, ni));
+        nv[i + 1] = load_at<T>(base, pick(link_sel(m, i + 1), own, pb32 + nj));
+        if (i + 2 < Q) base = uniform_opaque(base + 2 * pb);
+      }
+      m2 = mask_at(p + 1);
+    } else {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        nv[i] = load_at<T>(base, zb_[1 + D3Q19::cz[i]] + yb_[1 + D3Q19::cy[i]] +
+                                     xb_[1 + D3Q19::cx[i]]);
+        if (i + 1 < Q) base = uniform_opaque(base + pb);
+      }
+      nfl = SOLIDS ? flags[uint32_t(pz) * fl_z + fl_yx] : uint8_t(0);
     }
-    nfl = SOLIDS ? flags[uint32_t(pz) * fl_z + fl_yx] : uint8_t(0);
   };
   // own column's step-1 results: planes p - 1 (prev) and p - 2 (pp5)
   T prevv[Q], pp5 = T(0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) prevv[i] = T(0);
   uint8_t fl_prev = 0;
+  uint32_t m_prev = 0;
+  if constexpr (LINKS) m1 = mask_at(z0 - 1);
   issue(z0 - 1);
   for (int p = z0 - 1; p <= zend; ++p) {
     // ---- step 1 at (gx, gy, p): the single-step kernel's update ----
     const uint32_t ownb = uint32_t(wrap_mod(p, g.nz)) * zstride + own_yx;
-    const uint8_t fl = nfl;
+    if constexpr (LINKS) {
+      m0 = m1;
+      m1 = m2;
+    }
+    const uint8_t fl = LINKS ? uint8_t((m0 & kLinkSolid ? FLAG_SOLID : 0) |
+                                       (m0 & kLinkNoforce ? FLAG_NOFORCE : 0))
+                             : nfl;
     const bool solid = SOLIDS && (fl & FLAG_SOLID);
     C f[Q];
     bool mark[Q], mov[Q];
@@ -796,6 +865,7 @@ __global__ __launch_bounds__(64 * (tb2_rows<K>() + 3)) void k_step2(
     if (interior && q >= z0) {
       const uint32_t qownb = uint32_t(wrap_mod(q, g.nz)) * zstride + own_yx;
       const bool solid2 = SOLIDS && (fl_prev & FLAG_SOLID);
+      const uint32_t m_step2 = solid2 ? 0u : m_prev;  // LINKS: the links step 2 bounces back
       // plane q - c_z of direction i: p - 2 (c_z = +1, 3 slots), p - 1, p
       const uint32_t r3 = phase_base(p - 2, 3), r2 = phase_base(q, 2);
       C h[Q];
@@ -813,6 +883,9 @@ __global__ __launch_bounds__(64 * (tb2_rows<K>() + 3)) void k_step2(
           if (WALLS == 2 && raw_bits<K>(w) == Storage<K>::kMoving) bb += k.Kw[i];
           h[i] = bb;
         }
+        if (LINKS && i != 0)  // blocked link: the own cell's opposite population at plane q
+          h[i] = C(from_bits<K>(pick<typename Storage<K>::U>(
+              link_sel(m_step2, i), raw_bits<K>(prevv[D3Q19::opp[i]]), raw_bits<K>(w))));
       }
       if (FORCE && SOLIDS)
         collide<C, FORCE, K == ST_F16, INC, K == ST_F32>(h, k, (fl_prev & FLAG_NOFORCE) ? C(0) : C(1));
@@ -835,7 +908,30 @@ __global__ __launch_bounds__(64 * (tb2_rows<K>() + 3)) void k_step2(
 #pragma unroll
     for (int i = 0; i < Q; ++i) prevv[i] = cur[i];
     fl_prev = fl;
+    m_prev = m0;
   }
+}
+
+// The link mask of every cell for the two-step kernel's resting walls: bit i
+// (1..18) set when the pull along c_i is blocked (x - c_i solid, periodic),
+// plus the cell's own SOLID and NOFORCE flags.
+__global__ __launch_bounds__(kBlock) void k_link_mask(const uint8_t* __restrict__ flags,
+                                                      uint32_t* __restrict__ mask, Geo g) {
+  const size_t n = size_t(g.nx) * g.ny * g.nz;
+  const size_t idx = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (idx >= n) return;
+  const int x = int(idx % uint32_t(g.nx));
+  const size_t r = idx / uint32_t(g.nx);
+  const int y = int(r % uint32_t(g.ny)), z = int(r / uint32_t(g.ny));
+  const uint8_t fl = flags[idx];
+  uint32_t m = (fl & FLAG_SOLID ? kLinkSolid : 0u) | (fl & FLAG_NOFORCE ? kLinkNoforce : 0u);
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int xs = wrap_mod(x - D3Q19::cx[i], g.nx), ys = wrap_mod(y - D3Q19::cy[i], g.ny),
+              zs = wrap_mod(z - D3Q19::cz[i], g.nz);
+    if (flags[(size_t(zs) * g.ny + ys) * g.nx + xs] & FLAG_SOLID) m |= 1u << i;
+  }
+  mask[idx] = m;
 }
 
 // The separate obstacle kernel of the split design (WALLS = 3 steps): every
@@ -1540,36 +1636,39 @@ static Geo2 make_geo2(const Geo& g, int rows) {
 
 template <int K, int WALLS, bool FORCE, bool INC, bool MID = false>
 static void step2_t(const Geo& g, const PhysParams& ph, const void* src, void* dst,
-                    const uint8_t* flags, hipStream_t s, void* mid = nullptr) {
+                    const uint8_t* flags, const uint32_t* lmask, hipStream_t s,
+                    void* mid = nullptr) {
   using S = Storage<K>;
   constexpr int rows = tb2_rows<K>();
   const Geo2 h = make_geo2(g, rows);
   hipLaunchKernelGGL((k_step2<K, WALLS, FORCE, INC, MID>), dim3(h.nblocks), dim3(64 * (rows + 3)),
                      0, s, reinterpret_cast<const typename S::T*>(src),
                      reinterpret_cast<typename S::T*>(mid), reinterpret_cast<typename S::T*>(dst),
-                     flags, h, make_stepk<typename S::C>(ph));
+                     flags, lmask, h, make_stepk<typename S::C>(ph));
 }
 
 template <int K, int WALLS, bool INC>
 static void step2_f(bool force, const Geo& g, const PhysParams& ph, const void* src, void* dst,
-                    const uint8_t* flags, hipStream_t s) {
-  if (force) step2_t<K, WALLS, true, INC>(g, ph, src, dst, flags, s);
-  else step2_t<K, WALLS, false, INC>(g, ph, src, dst, flags, s);
+                    const uint8_t* flags, const uint32_t* lmask, hipStream_t s) {
+  if (force) step2_t<K, WALLS, true, INC>(g, ph, src, dst, flags, lmask, s);
+  else step2_t<K, WALLS, false, INC>(g, ph, src, dst, flags, lmask, s);
 }
 
+// walls: none (0), resting with markers (1) or with the link mask (4), moving (2)
 template <int K, bool INC>
 static void step2_w(bool solids, bool force, const Geo& g, const PhysParams& ph, const void* src,
-                    void* dst, const uint8_t* flags, hipStream_t s) {
-  if (!solids) step2_f<K, 0, INC>(force, g, ph, src, dst, flags, s);
-  else if (!ph.moving) step2_f<K, 1, INC>(force, g, ph, src, dst, flags, s);
-  else step2_f<K, 2, INC>(force, g, ph, src, dst, flags, s);
+                    void* dst, const uint8_t* flags, const uint32_t* lmask, hipStream_t s) {
+  if (!solids) step2_f<K, 0, INC>(force, g, ph, src, dst, flags, lmask, s);
+  else if (!ph.moving && lmask) step2_f<K, 4, INC>(force, g, ph, src, dst, flags, lmask, s);
+  else if (!ph.moving) step2_f<K, 1, INC>(force, g, ph, src, dst, flags, lmask, s);
+  else step2_f<K, 2, INC>(force, g, ph, src, dst, flags, lmask, s);
 }
 
 template <int K>
 static void step2_k(bool solids, bool force, const Geo& g, const PhysParams& ph, const void* src,
-                    void* dst, const uint8_t* flags, hipStream_t s) {
-  if (ph.incomp) step2_w<K, true>(solids, force, g, ph, src, dst, flags, s);
-  else step2_w<K, false>(solids, force, g, ph, src, dst, flags, s);
+                    void* dst, const uint8_t* flags, const uint32_t* lmask, hipStream_t s) {
+  if (ph.incomp) step2_w<K, true>(solids, force, g, ph, src, dst, flags, lmask, s);
+  else step2_w<K, false>(solids, force, g, ph, src, dst, flags, lmask, s);
 }
 
 int step2_blocks(int storage, const Geo& g) {
@@ -1584,13 +1683,14 @@ int step2_blocks(int storage, const Geo& g) {
 }
 
 hipError_t launch_step2(int storage, bool solids, bool force, const Geo& g, const PhysParams& ph,
-                        const void* src, void* dst, const uint8_t* flags, hipStream_t s) {
+                        const void* src, void* dst, const uint8_t* flags, const uint32_t* lmask,
+                        hipStream_t s) {
   switch (storage) {
-    case ST_F32: step2_k<ST_F32>(solids, force, g, ph, src, dst, flags, s); break;
-    case ST_F16: step2_k<ST_F16>(solids, force, g, ph, src, dst, flags, s); break;
-    case ST_BF16: step2_k<ST_BF16>(solids, force, g, ph, src, dst, flags, s); break;
-    case ST_F64: step2_k<ST_F64>(solids, force, g, ph, src, dst, flags, s); break;
-    case ST_F32X: step2_k<ST_F32X>(solids, force, g, ph, src, dst, flags, s); break;
+    case ST_F32: step2_k<ST_F32>(solids, force, g, ph, src, dst, flags, lmask, s); break;
+    case ST_F16: step2_k<ST_F16>(solids, force, g, ph, src, dst, flags, lmask, s); break;
+    case ST_BF16: step2_k<ST_BF16>(solids, force, g, ph, src, dst, flags, lmask, s); break;
+    case ST_F64: step2_k<ST_F64>(solids, force, g, ph, src, dst, flags, lmask, s); break;
+    case ST_F32X: step2_k<ST_F32X>(solids, force, g, ph, src, dst, flags, lmask, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1600,26 +1700,34 @@ hipError_t launch_step2(int storage, bool solids, bool force, const Geo& g, cons
 // adjoint's storage): src = f*(t) -> mid = f*(t+1), dst = f*(t+2).
 template <int WALLS, bool INC>
 static void step2_mid_f(bool force, const Geo& g, const PhysParams& ph, const void* src, void* mid,
-                        void* dst, const uint8_t* flags, hipStream_t s) {
-  if (force) step2_t<ST_F32, WALLS, true, INC, true>(g, ph, src, dst, flags, s, mid);
-  else step2_t<ST_F32, WALLS, false, INC, true>(g, ph, src, dst, flags, s, mid);
+                        void* dst, const uint8_t* flags, const uint32_t* lmask, hipStream_t s) {
+  if (force) step2_t<ST_F32, WALLS, true, INC, true>(g, ph, src, dst, flags, lmask, s, mid);
+  else step2_t<ST_F32, WALLS, false, INC, true>(g, ph, src, dst, flags, lmask, s, mid);
 }
 
 template <bool INC>
 static void step2_mid_w(bool solids, bool force, const Geo& g, const PhysParams& ph,
                         const void* src, void* mid, void* dst, const uint8_t* flags,
-                        hipStream_t s) {
-  if (!solids) step2_mid_f<0, INC>(force, g, ph, src, mid, dst, flags, s);
-  else if (!ph.moving) step2_mid_f<1, INC>(force, g, ph, src, mid, dst, flags, s);
-  else step2_mid_f<2, INC>(force, g, ph, src, mid, dst, flags, s);
+                        const uint32_t* lmask, hipStream_t s) {
+  if (!solids) step2_mid_f<0, INC>(force, g, ph, src, mid, dst, flags, lmask, s);
+  else if (!ph.moving && lmask) step2_mid_f<4, INC>(force, g, ph, src, mid, dst, flags, lmask, s);
+  else if (!ph.moving) step2_mid_f<1, INC>(force, g, ph, src, mid, dst, flags, lmask, s);
+  else step2_mid_f<2, INC>(force, g, ph, src, mid, dst, flags, lmask, s);
 }
 
 hipError_t launch_step2_mid(int storage, bool solids, bool force, const Geo& g,
                             const PhysParams& ph, const void* src, void* mid, void* dst,
-                            const uint8_t* flags, hipStream_t s) {
+                            const uint8_t* flags, const uint32_t* lmask, hipStream_t s) {
   if (storage != ST_F32) return hipErrorInvalidValue;
-  if (ph.incomp) step2_mid_w<true>(solids, force, g, ph, src, mid, dst, flags, s);
-  else step2_mid_w<false>(solids, force, g, ph, src, mid, dst, flags, s);
+  if (ph.incomp) step2_mid_w<true>(solids, force, g, ph, src, mid, dst, flags, lmask, s);
+  else step2_mid_w<false>(solids, force, g, ph, src, mid, dst, flags, lmask, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_link_mask(const Geo& g, const uint8_t* flags, uint32_t* mask, hipStream_t s) {
+  const size_t n = size_t(g.nx) * g.ny * g.nz;
+  hipLaunchKernelGGL(k_link_mask, dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     flags, mask, g);
   return hipGetLastError();
 }
 

@@ -217,3 +217,24 @@ def test_steps_per_pass_option():
     with pytest.raises(A.LBMError) as e:
         A.lbm_query(A.params((4, 4, 4), 0.6, steps_per_pass=2, obstacle_kernel=1))
     assert e.value.status == A.LBM_E_UNSUPPORTED
+
+
+def test_scratch_holds_the_link_mask_where_pairs_may_run():
+    """scratch_bytes: the reduction's partials, plus 4 bytes per cell (the
+    two-step pass's link mask) when steps_per_pass is 2 or automatic -- not
+    with single steps, the split design, or where a pair of direction arrays
+    would span 4 GiB (the pass then keeps the marker test)."""
+    shape = (10, 20, 30)
+    sb = lambda **kw: A.lbm_query(A.params(shape, 0.6, **kw))[3]
+    base = sb()
+    assert base % 256 == 0 and sb(steps_per_pass=1) == base
+    mask = (10 * 20 * 30 * 4 + 255) // 256 * 256
+    assert sb(steps_per_pass=2) == base + mask
+    assert sb(steps_per_pass="auto") == base + mask
+    assert sb(steps_per_pass="auto", obstacle_kernel=1) == base
+    # 1023^3 FP32 (x_stride 1024): one direction array fits 4 GiB, two do not
+    big = A.lbm_query(A.params((1023, 1023, 1023), 0.6, steps_per_pass=2))[3]
+    assert big == base
+    # 768^3 FP32: two arrays of 1.8 GB, the mask is 1.8 GB
+    large = A.lbm_query(A.params((768, 768, 768), 0.6, steps_per_pass=2))[3]
+    assert large == base + 768 ** 3 * 4

@@ -101,7 +101,7 @@ def test_trace_summary_two_steps_per_launch(tmp_path, capsys):
     """A headline of two steps per launch is checked against the two-step
     kernel's launches: warm-up and timed steps count in pairs."""
     b = _bench()
-    k2 = "void lbm::k_step2<0, 1, true, false, false>"
+    k2 = "void lbm::k_step2<0, 4, true, false, false>"
     g = b.launch_threads(k2, 512)
     assert b.box_of(k2, g) == 512
     kp = "void lbm::k_step2<0, 0, true, false, true>"  # periodic: the adjoint's 256^3 box

@@ -92,6 +92,29 @@ def test_two_step_pass_unpadded_and_without_force(storage):
     assert two.x_stride == 65 and _same(one, two)
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
+def test_two_step_pass_follows_changed_flags(storage):
+    """Cells turned solid after some steps (the flags changed in place, then
+    lbm_refresh_solids): the pass's link mask follows the new geometry, and
+    pairs still equal single steps bit for bit."""
+    shape = (12, 14, 70)
+    say("two-step pass after a change of the flags", storage)
+    fl = I.random_flags(shape, 21, solid_fraction=0.1, noforce_fraction=0.1)
+    u0 = _u0(shape, 22)
+    u0[:, torch.from_numpy(fl & 1 == 1)] = 0
+    s = 10 if storage == "f16" else 0
+    sims = [LBM(shape, 0.6, (1e-5, 0, 0), storage, flags=fl, u0=u0, f16_scale_log2=s,
+                steps_per_pass=spp).step(4) for spp in (0, 2)]
+    more = (I.random_flags(shape, 23, solid_fraction=0.05) & 1).astype(np.uint8)
+    for sim in sims:
+        sim.flags |= torch.from_numpy(more).cuda()
+        sim.refresh_solids()
+        sim.step(6)
+    torch.cuda.synchronize()
+    assert _same(*sims)
+    check_solids(sims[1], fl | more)
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_two_step_pass_with_graph_replays(storage):
     """Graphs of 6 steps (three fused passes: the replay ends on the other
