@@ -1,6 +1,9 @@
 """The two-step pass (steps_per_pass = 2: pairs of steps fused into one
-temporally blocked kernel that keeps the intermediate level on chip) gives
-the same bits as single steps -- every storage, resting and moving walls,
+temporally blocked kernel that keeps the intermediate level on chip; resting
+walls through the link mask, moving walls and oversized grids through the
+markers) gives the same bits as single steps -- every storage, resting walls
+(sparse and dense), moving walls, moving-wall flags at zero wall velocity,
+a change of the flags after some steps,
 no-force cells, both equilibria, ragged and degenerate shapes, several z
 chunks, the unpadded layout, graph replays, odd step counts -- and the
 oracle's result within the FP32 bar; at the benchmark's full size as well."""
@@ -60,6 +63,8 @@ CASES = {
     "single_cell": ((1, 1, 1), None),
     "thin_slab": ((1, 5, 1), None),
     "narrow": ((3, 2, 17), "flags"),
+    "dense_solids": ((11, 13, 90), "dense"),
+    "moving_flags_at_rest": ((10, 12, 70), "moving_at_rest"),
 }
 
 
@@ -74,6 +79,11 @@ def test_two_step_pass_is_bit_identical(storage, case):
     elif geo == "moving":
         fl = I.random_flags(shape, 10, solid_fraction=0.15, noforce_fraction=0.1) | I.cavity_flags(shape)
         kw.update(flags=fl, wall_u=(0.04, -0.01, 0.02))
+    elif geo == "dense":  # most links blocked
+        kw["flags"] = I.random_flags(shape, 19, solid_fraction=0.6, noforce_fraction=0.1)
+    elif geo == "moving_at_rest":  # moving-wall flags, zero wall velocity: resting walls
+        kw["flags"] = (I.random_flags(shape, 20, solid_fraction=0.15, noforce_fraction=0.1)
+                       | I.cavity_flags(shape))
     if "flags" in kw:
         kw["u0"][:, torch.from_numpy(kw["flags"] & 1 == 1)] = 0
     for eq in ("qian", "incompressible"):
