@@ -49,6 +49,8 @@
  *    moving-wall marker.  Any other value is data: a NaN or infinity that
  *    arises in a fluid cell (a 16-bit overflow, corrupted input) enters the
  *    neighbours' collisions and so reaches lbm_reduce as a non-finite sum.
+ *    (The two-step pass at resting walls decides the same bounce-backs
+ *    from a link mask built from the flags instead, with the same results.)
  *    Padding stays 0.  The library maintains the markers itself (init, step,
  *    save/restore); after writing a grid from outside, call
  *    lbm_refresh_solids.  Fluid values must never carry a marker pattern.
