@@ -920,9 +920,9 @@ def main():
     if "large" in legs:
         del flags_t
         torch.cuda.empty_cache()
-        log("large 768^3 f32 (single steps, fused pairs), 640^3 f64")
+        log("large 768^3 f32 and 640^3 f64 (single steps, fused pairs)")
         res["large"] = [large_leg(torch, "f32", 768), large_leg(torch, "f32", 768, steps_per_pass=2),
-                        large_leg(torch, "f64", 640)]
+                        large_leg(torch, "f64", 640), large_leg(torch, "f64", 640, steps_per_pass=2)]
     if "cpu" in legs:
         log("cpu oracle sample")
         res["cpu"] = cpu_leg(flags, args.cpu_seconds)
