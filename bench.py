@@ -563,12 +563,12 @@ KERNELS = {  # record key -> (kernel name, box edge, bytes per fluid update, por
 def launch_threads(name, n):
     """Threads a launch of the named kernel has on an n^3 box (64 * M-cell
     segments per row, four per block, M = 4 for the 16-bit step kernels; the
-    two-step kernel: 64 x TY tiles (TY = 13; 4 for FP64, 8 for F32X), z
+    two-step kernel: 64 x TY tiles (TY = 13; 5 for FP64, 8 for F32X), z
     chunks of 128 planes halved down to 16 until there are 1280 blocks,
     64 (TY + 3) threads per block)."""
     if name.startswith("void lbm::k_step2<"):
         k = int(name.split("<")[1].split(",")[0])
-        ty = {3: 4, 4: 8}.get(k, 13)
+        ty = {3: 5, 4: 8}.get(k, 13)
         tiles = -(-n // 64) * -(-n // ty)
         zc = min(n, 128)
         while zc > 16 and tiles * -(-n // zc) < 1280:

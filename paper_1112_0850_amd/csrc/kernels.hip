@@ -568,9 +568,11 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 // previous plane and stay in its registers (an LDS read there would wait
 // behind the marker test of the pulled value); so do the three populations
 // that do not move in x or y (0 and the pure-z pair).  The ring holds as
-// many planes of a direction as they are read: c_z = +1 two planes later
-// (3 slots), c_z = 0 and c_z = -1 up to one plane later (2 slots); two
-// barriers per plane separate writes from reads.  The next plane's 19 pulls are issued before the first barrier,
+// many planes of a direction as are live: step 2 at plane p - 1 reads
+// direction i at plane p - 1 - c_z, so c_z = +1 is read two planes after it
+// was written (3 slots), c_z = 0 one plane after (2 slots) and c_z = -1 in
+// the same iteration (1 slot); two barriers per plane separate writes from
+// reads.  The next plane's 19 pulls are issued before the first barrier,
 // so their latency hides behind step 2.  Both steps run the single-step
 // kernel's pull, marker test, collision and rounding, and the intermediate
 // values are rounded to the storage type, so a pass equals two single steps
@@ -579,7 +581,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 // traffic per pass: one read of f*(t) (plus the halo lines that miss in L2)
 // and one write of f*(t+2) -- about half of two single steps.
 // ---------------------------------------------------------------------------
-constexpr int kTB2Arrays = 36;  // LDS plane-arrays of [TY + 2][66]
+constexpr int kTB2Arrays = 32;  // LDS plane-arrays of [TY + 2][66]
 // link-mask bits besides the 18 links (bit i: the pull along c_i is blocked)
 constexpr uint32_t kLinkSolid = 1u << 19;
 constexpr uint32_t kLinkNoforce = 1u << 20;
@@ -610,15 +612,17 @@ constexpr int kTB2MinChunk = 16;   // shortest z chunk
 constexpr int kTB2MinBlocks = 1280;  // five blocks per CU on 256 CUs
 
 // Tile rows per block: 13 (16 waves, 1024 threads, one block per CU: the
-// FP32 ring takes 143 KB of LDS) for 4- and 2-byte storage, which fit 128
+// FP32 ring takes 127 KB of LDS) for 4- and 2-byte storage, which fit 128
 // VGPRs without spills; measured at 512^3, 13 rows beat 12, 8, 6 and 5.
-// FP64 storage takes 4 so that its ring fits in LDS, and F32X (FP64
-// arithmetic) 8, whose 11 waves may use 168 VGPRs.
+// FP64 storage takes 5, the most whose ring fits in LDS (118 KB), and F32X
+// (FP64 arithmetic) 8, whose 11 waves may use 168 VGPRs.
 template <int K>
 __host__ __device__ constexpr int tb2_rows() {
-  return K == ST_F64 ? 4 : (K == ST_F32X ? 8 : 13);
+  return K == ST_F64 ? 5 : (K == ST_F32X ? 8 : 13);
 }
-__host__ __device__ constexpr int tb2_nslot(int i) { return D3Q19::cz[i] > 0 ? 3 : 2; }
+__host__ __device__ constexpr int tb2_nslot(int i) {
+  return D3Q19::cz[i] > 0 ? 3 : (D3Q19::cz[i] == 0 ? 2 : 1);
+}
 // first plane-array of direction i (the 16 directions with c_x or c_y != 0)
 __host__ __device__ constexpr int tb2_base(int i) {
   int b = 0;
@@ -834,7 +838,7 @@ __global__ __launch_bounds__(64 * (tb2_rows<K>() + 3)) void k_step2(
     else
       collide<C, FORCE, K == ST_F16, INC, K == ST_F32>(f, k, C(1));
     const T marker = solid_marker<K>(fl, WALLS == 2);
-    const uint32_t w2 = phase_base(p, 2), w3 = phase_base(p, 3);
+    const uint32_t w1 = lane_opaque(lane_b), w2 = phase_base(p, 2), w3 = phase_base(p, 3);
     T cur[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -845,7 +849,8 @@ __global__ __launch_bounds__(64 * (tb2_rows<K>() + 3)) void k_step2(
       if (i != 0 && i != 5 && i != 6) {
         const int tx = ex + D3Q19::cx[i], ty = ey + D3Q19::cy[i];
         if (tx >= -1 && tx <= TX && ty >= -1 && ty <= TY)
-          ring_at(tb2_nslot(i) == 3 ? w3 : w2, i, D3Q19::cy[i], D3Q19::cx[i]) = v;
+          ring_at(tb2_nslot(i) == 3 ? w3 : (tb2_nslot(i) == 2 ? w2 : w1), i, D3Q19::cy[i],
+                  D3Q19::cx[i]) = v;
       }
     }
     if constexpr (MID) {
@@ -875,7 +880,7 @@ __global__ __launch_bounds__(64 * (tb2_rows<K>() + 3)) void k_step2(
         if (i == 0) w = prevv[0];
         else if (i == 5) w = pp5;
         else if (i == 6) w = cur[6];
-        else w = ring_at(D3Q19::cz[i] > 0 ? r3 : (D3Q19::cz[i] == 0 ? r2 : w2), i, 0, 0);
+        else w = ring_at(D3Q19::cz[i] > 0 ? r3 : (D3Q19::cz[i] == 0 ? r2 : w1), i, 0, 0);
         h[i] = C(w);
         if (MARKERS && i != 0 && is_marker<K, WALLS>(raw_bits<K>(w)) && !solid2) {
           // half-way bounce-back: the own cell's opposite population at plane q
