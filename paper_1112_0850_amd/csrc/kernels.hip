@@ -614,8 +614,9 @@ constexpr int kTB2MinBlocks = 1280;  // five blocks per CU on 256 CUs
 // Tile rows per block: 13 (16 waves, 1024 threads, one block per CU: the
 // FP32 ring takes 127 KB of LDS) for 4- and 2-byte storage, which fit 128
 // VGPRs without spills; measured at 512^3, 13 rows beat 12, 8, 6 and 5.
-// FP64 storage takes 5, the most whose ring fits in LDS (118 KB), and F32X
-// (FP64 arithmetic) 8, whose 11 waves may use 168 VGPRs.
+// FP64 storage takes 5 (118 KB of LDS; 6 rows cap the 9 waves at 168
+// VGPRs, spill and ran 0.7% slower), and F32X (FP64 arithmetic) 8, whose 11
+// waves may use 168 VGPRs.
 template <int K>
 __host__ __device__ constexpr int tb2_rows() {
   return K == ST_F64 ? 5 : (K == ST_F32X ? 8 : 13);
