@@ -64,6 +64,7 @@ CASES = {
     "thin_slab": ((1, 5, 1), None),
     "narrow": ((3, 2, 17), "flags"),
     "dense_solids": ((11, 13, 90), "dense"),
+    "tiny_porous": ((2, 1, 3), "tiny"),  # every pull wraps onto the box itself
     "moving_flags_at_rest": ((10, 12, 70), "moving_at_rest"),
 }
 
@@ -79,6 +80,11 @@ def test_two_step_pass_is_bit_identical(storage, case):
     elif geo == "moving":
         fl = I.random_flags(shape, 10, solid_fraction=0.15, noforce_fraction=0.1) | I.cavity_flags(shape)
         kw.update(flags=fl, wall_u=(0.04, -0.01, 0.02))
+    elif geo == "tiny":  # one solid cell, one no-force cell
+        fl = np.zeros(shape, dtype=np.uint8)
+        fl[0, 0, 1] = I.FLAG_SOLID
+        fl[1, 0, 2] = I.FLAG_NOFORCE
+        kw["flags"] = fl
     elif geo == "dense":  # most links blocked
         kw["flags"] = I.random_flags(shape, 19, solid_fraction=0.6, noforce_fraction=0.1)
     elif geo == "moving_at_rest":  # moving-wall flags, zero wall velocity: resting walls
