@@ -152,7 +152,8 @@ class LBM:
 
     def refresh_solids(self):
         """Rewrite the solid-cell markers of the current grid (after
-        populations were written into it directly)."""
+        populations were written into it directly) and the two-step pass's
+        link mask (after the flags were changed in place)."""
         A.lbm_refresh_solids(self.ctx)
 
     def set_current(self, parity, t):
