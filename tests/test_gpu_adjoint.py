@@ -236,9 +236,9 @@ def test_fused_recomputation_gives_identical_gradients(monkeypatch):
     u0[:, flags & 1 == 1] = 0
     target = _f32(I.smooth_field(n, 16, amplitude=0.02, modes=3))
     F = np.array([2e-5, 0, -1e-5])
-    for k in (6, 9):
+    for k, spp in ((6, 0), (9, 0), (6, 2)):  # spp = 2: the link mask in the recomputation
         monkeypatch.setattr(L, "FUSED_RECOMPUTE_MIN_CELLS", 1 << 40)
         ref = _gpu_grad(u0, target, F, flags, tau, steps, k)
         monkeypatch.setattr(L, "FUSED_RECOMPUTE_MIN_CELLS", 0)
-        got = _gpu_grad(u0, target, F, flags, tau, steps, k)
+        got = _gpu_grad(u0, target, F, flags, tau, steps, k, steps_per_pass=spp)
         assert got[2] == ref[2] and np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), k

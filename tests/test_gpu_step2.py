@@ -306,11 +306,13 @@ def test_two_step_pass_at_maximum_size():
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("spp", [0, 2])
 @pytest.mark.parametrize("case", ["porous", "moving_walls", "incompressible", "periodic_ragged"])
-def test_step2_from_stores_both_states(case):
+def test_step2_from_stores_both_states(case, spp):
     """lbm_step2_from (the adjoint's recomputation): mid == one step_from,
     dst == two, bit for bit, on arbitrary grids; the context's own grids and
-    time are untouched."""
+    time are untouched.  spp = 2: a context made for pairs, whose resting
+    walls go through the link mask."""
     shape = (21, 17, 70) if case == "periodic_ragged" else (12, 15, 66)
     say("step2_from", case, shape)
     kw = dict(u0=_u0(shape, 11))
@@ -323,7 +325,8 @@ def test_step2_from_stores_both_states(case):
     if "flags" in kw:
         kw["u0"][:, torch.from_numpy(kw["flags"] & 1 == 1)] = 0
     eq = "incompressible" if case == "incompressible" else "qian"
-    sim = LBM(shape, 0.62, (3e-5, -1e-5, 2e-5), "f32", equilibrium=eq, **kw).step(3)
+    sim = LBM(shape, 0.62, (3e-5, -1e-5, 2e-5), "f32", equilibrium=eq, steps_per_pass=spp,
+              **kw).step(3)
     src = sim.grids[sim.current].clone()
     t0, cur0 = sim.t, sim.current
     a1, a2, m, d = (sim.new_grid() for _ in range(4))
