@@ -574,7 +574,8 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename Storage<K>::T* _
 // the same iteration (1 slot); two barriers per plane separate writes from
 // reads.  The next plane's 19 pulls are issued before the first barrier,
 // so their latency hides behind step 2.  Both steps run the single-step
-// kernel's pull, marker test, collision and rounding, and the intermediate
+// kernel's pull, bounce-back (the marker test, or the link mask at resting
+// walls: WALLS = 4 below), collision and rounding, and the intermediate
 // values are rounded to the storage type, so a pass equals two single steps
 // bit for bit.  Threads: TY + 2 waves, one per extended row (lane = x), plus
 // one wave for the 2 (TY + 2) halo cells left and right of the tile.  HBM
