@@ -131,6 +131,29 @@ def test_two_step_pass_follows_changed_flags(storage):
     check_solids(sims[1], fl | more)
 
 
+def test_link_mask_content():
+    """The link mask the two-step pass reads, read back from the context's
+    scratch (after the reduction's partials): bit i set exactly when the pull
+    along c_i comes from a solid cell (periodic), bit 19 SOLID, bit 20
+    NOFORCE -- against the same rule written out from the flags in numpy."""
+    shape = (7, 9, 70)
+    fl = I.random_flags(shape, 31, solid_fraction=0.2, noforce_fraction=0.15)
+    sim = LBM(shape, 0.6, (1e-5, 0, 0), "f32", flags=fl, steps_per_pass=2)
+    torch.cuda.synchronize()
+    cells = int(np.prod(shape))
+    off = (1024 * 5 * 8 + 255) // 256 * 256  # the reduction's 1024 x 5 FP64 partials
+    got = sim.scratch.view(torch.uint8)[off:off + 4 * cells].view(torch.int32).cpu().numpy()
+    got = got.view(np.uint32).reshape(shape)
+    e, _, _ = O.lattice()
+    solid = (fl & 1) == 1
+    want = np.where(solid, 1 << 19, 0).astype(np.uint32) | np.where(fl & 2, 1 << 20, 0).astype(np.uint32)
+    for i in range(1, 19):
+        cx, cy, cz = (int(v) for v in e[i])
+        src = np.roll(solid, (cz, cy, cx), axis=(0, 1, 2))  # solid(x - c_i)
+        want |= np.where(src, np.uint32(1 << i), np.uint32(0))
+    assert np.array_equal(got, want)
+
+
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_two_step_pass_with_graph_replays(storage):
     """Graphs of 6 steps (three fused passes: the replay ends on the other
