@@ -238,3 +238,7 @@ def test_scratch_holds_the_link_mask_where_pairs_may_run():
     # 768^3 FP32: two arrays of 1.8 GB, the mask is 1.8 GB
     large = A.lbm_query(A.params((768, 768, 768), 0.6, steps_per_pass=2))[3]
     assert large == base + 768 ** 3 * 4
+    # FP64: 640^3 (two arrays of 2.1 GB: 4.19 GB < 4 GiB) has the mask, 650^3
+    # (704-cell rows: two arrays of 2.4 GB) does not
+    f64 = lambda n: A.lbm_query(A.params((n, n, n), 0.6, storage=A.LBM_F64, steps_per_pass=2))[3]
+    assert f64(640) == base + 640 ** 3 * 4 and f64(650) == base
